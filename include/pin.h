@@ -1,0 +1,145 @@
+/*
+ * pin.h -- C ABI of libpin: the collapse-time path of PINOCCHIO (Monaco et al. 2013,
+ * arXiv:1305.1505) on AMD Instinct MI355X (gfx950).
+ *
+ * The path (section "Collapse times" of the paper):
+ *   1. a Gaussian linear density field delta_l on an N^3 Lagrangian grid of side L, normalised so
+ *      that its top-hat variance at 8 Mpc/h is sigma_8^2 (eq. deltal and the paragraph after it);
+ *   2. for each Gaussian smoothing radius R, the deformation tensor T_ij = d_i d_j phi with
+ *      lap(phi) = delta_l, obtained with FFTs;
+ *   3. for each grid point, the inverse collapse time F = 1/D(t_coll) (eq. F) of the ellipsoidal
+ *      collapse model (truncated 3rd-order LPT with a quasi-spherical correction);
+ *   4. for each grid point, the maximum F over the radii, F_max, and the radius R_max where it
+ *      was reached (the trajectory maximum);
+ *   5. the closing Zel'dovich and 2LPT displacement fields.
+ *
+ * Conventions shared by every entry point
+ *   - Grids are C order, z fastest.  A "half spectrum" is complex [N][N][N/2+1] (the layout of a
+ *     real-to-complex 3D FFT); a "real field" is [N][N][N].  Complex numbers are interleaved
+ *     (re, im) pairs of the plan's precision: float for PIN_FP32, double for PIN_FP64.
+ *   - The forward transform is unnormalised: a real field x has spectrum
+ *     X(k) = sum_q x(q) exp(-2 pi i k.q/N); the inverse carries 1/N^3.
+ *   - Integer frequencies f = 0..N/2-1, -N/2..-1 on x and y, 0..N/2 on z; k = 2 pi f / L (h/Mpc).
+ *     Every mode with a Nyquist index carries no derivative and is treated as zero.
+ *   - Radii are in grid cells (R_phys = R * L / N); the window is W(kR) = exp(-k^2 R^2 / 2).
+ *   - Device pointers are caller-owned (the library never frees them) and must stay valid until
+ *     the work queued on `stream` completes.  Every call is ordered on `stream` (NULL = the null
+ *     stream) and returns without waiting for the GPU.
+ *   - Arguments are validated before anything is queued: on an error status nothing was written.
+ *     A plan is not thread-safe; distinct plans may be used from distinct threads.
+ *   - Errors: every function returns a pin_status; pin_last_error() returns a thread-local
+ *     message for the last failure on the calling thread.
+ */
+#ifndef PIN_H
+#define PIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIN_OK = 0,
+  PIN_ERR_INVALID_ARG = 1,      /* a NULL pointer, a bad size, an unordered radius list, ... */
+  PIN_ERR_UNSUPPORTED_SIZE = 2, /* N not in the supported set (pin_size_supported)           */
+  PIN_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed                                  */
+  PIN_ERR_DEVICE = 4,           /* a HIP call or kernel launch failed                        */
+  PIN_ERR_NOT_READY = 5,        /* serving: the result is not ready yet                      */
+  PIN_ERR_BUDGET = 6,           /* serving: the request can never fit the HBM budget         */
+  PIN_ERR_CANCELLED = 7,        /* serving: the request was cancelled                        */
+  PIN_ERR_SHUTDOWN = 8,         /* serving: the server is shutting down                      */
+  PIN_ERR_TIMEOUT = 9           /* serving: a wait timed out                                 */
+} pin_status;
+
+typedef enum {
+  PIN_FP32 = 0, /* complex64 FFTs and spectral multiplies (FP64-computed twiddles and windows);
+                   float64 for the eigenvalue near degeneracy and for the collapse root        */
+  PIN_FP64 = 1  /* complex128 FFTs, float64 throughout                                        */
+} pin_precision;
+
+typedef struct pin_plan_s* pin_plan;
+
+/* Problem description (section "Collapse times"): grid, box, radii and spectrum. */
+typedef struct {
+  int n;                     /* grid points per side; even, of the form 2^a 3^b, 8..1536     */
+  double box;                /* side L in Mpc/h, > 0                                          */
+  int n_radii;               /* 1..254                                                        */
+  const double* radii_cells; /* host array of n_radii radii in cells, > 0, strictly decreasing
+                                (largest first); copied by pin_plan_create                     */
+  double sigma8;             /* top-hat rms at 8 Mpc/h, > 0 (workloads: 0.8)                  */
+  double gamma;              /* BBKS shape parameter, > 0 (workloads: 0.21)                   */
+  double ns;                 /* primordial slope of P(k) = A k^ns T_BBKS(k/gamma)^2 (1.0)     */
+  pin_precision prec;
+} pin_plan_desc;
+
+/* Whether N is a supported grid size (1) or not (0). Host only. */
+int pin_size_supported(int n);
+
+/* Device bytes pin_plan_create allocates for `desc` (workspace, tables); host only. */
+pin_status pin_plan_workspace_bytes(const pin_plan_desc* desc, size_t* bytes);
+
+/* Validate `desc` without touching the GPU. */
+pin_status pin_plan_validate(const pin_plan_desc* desc);
+
+/* Create a plan on the current HIP device: computes the sigma_8 amplitude, the FP64 twiddle and
+ * window tables, and allocates the FFT workspace.  *out receives the handle. */
+pin_status pin_plan_create(const pin_plan_desc* desc, pin_plan* out);
+
+/* Free the plan and its device memory (waits for the device to go idle first). */
+pin_status pin_plan_destroy(pin_plan plan);
+
+/* eq. deltal: write the seeded Gaussian linear field's half spectrum to `dk` (device,
+ * N*N*(N/2+1) complex).  Each half-space mode (i, j, l) takes two uniforms from Philox4x32-10
+ * (Salmon et al., SC'11) with counter (i*N + j)*(N/2+1) + l split into (low, high) 32-bit words
+ * and key = seed split likewise; a uniform is (2*(w >> 12) + 1)*2^-53 from the 64-bit words
+ * w = c1:c0 and c3:c2; Box-Muller gives g1 + i g2 and dk = sqrt(P(k) N^6 / (2 L^3)) (g1 + i g2).
+ * On the l = 0 plane the member of each (f, -f) pair with the larger i*N + j is drawn and the
+ * other is its conjugate; k = 0 and every Nyquist mode are zero. */
+pin_status pin_generate_field(pin_plan plan, uint64_t seed, void* dk, hipStream_t stream);
+
+/* Set F (device, N^3 of the plan's real type) to 0 and ridx (device, N^3 bytes) to 255. */
+pin_status pin_collapse_reset(pin_plan plan, void* F, uint8_t* ridx, hipStream_t stream);
+
+/* Trajectory maximum over radii [r_begin, r_end) (0 <= r_begin < r_end <= n_radii), updating
+ * the running state (F, ridx) in place: for each radius r in order and each grid point, if the
+ * inverse collapse time F(q; R_r) is strictly larger than F[q], F[q] <- F(q; R_r) and
+ * ridx[q] <- r.  dk is the half spectrum (device).  Splitting [0, n_radii) into consecutive
+ * ranges gives the same result as one call. */
+pin_status pin_collapse_times_range(pin_plan plan, const void* dk, void* F, uint8_t* ridx,
+                                    int r_begin, int r_end, hipStream_t stream);
+
+/* pin_collapse_reset followed by pin_collapse_times_range over all radii: F_max and the index
+ * of R_max (255 where no radius gives a positive F). */
+pin_status pin_collapse_times(pin_plan plan, const void* dk, void* F, uint8_t* ridx,
+                              hipStream_t stream);
+
+/* The six deformation-tensor components at radius index r (r = -1: unsmoothed), written to T6
+ * (device, [6][N][N][N] real, order xx, xy, xz, yy, yz, zz). */
+pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6,
+                                  hipStream_t stream);
+
+/* Closing displacements at D = 1 in Mpc/h, each [3][N][N][N] real (components x, y, z):
+ * psi1 = Zel'dovich, psi1(k) = i k dk / k^2;  psi2 = EdS 2LPT, psi2(k) = (3/7) i k mu2~(k) / k^2
+ * with mu2 = sum_{i<j} (T_ii T_jj - T_ij^2) of the unsmoothed tensor and mu2~ its forward
+ * transform (k = 0 and Nyquist modes zeroed).  Either output may be NULL to skip it. */
+pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* psi2,
+                             hipStream_t stream);
+
+/* Per-kernel timing with HIP events recorded around every launch of the plan on its stream.
+ * Kernel classes are numbered 0..pin_kernel_class_count()-1 and named by pin_kernel_class_name. */
+int pin_kernel_class_count(void);
+const char* pin_kernel_class_name(int cls);
+pin_status pin_plan_set_timing(pin_plan plan, int enable); /* enabling also resets the totals   */
+/* Waits for the recorded events, then returns the summed duration (ms) and launch count. */
+pin_status pin_plan_kernel_time(pin_plan plan, int cls, double* total_ms, long long* launches);
+
+const char* pin_status_string(pin_status status);
+const char* pin_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIN_H */

@@ -1,0 +1,242 @@
+"""ctypes binding of libpin (include/pin.h): argument marshalling only.
+
+Every ``pin_*`` function here has the C entry point's name and arguments; device buffers are
+passed as integer addresses (e.g. ``tensor.data_ptr()``) and streams as integer HIP stream
+handles (``torch.cuda.current_stream().cuda_stream``; 0 = the null stream).  A non-OK status
+raises :class:`PinError`.  Importing this module loads ``libpin.so`` and raises ImportError if
+it has not been built -- there is no fallback path.
+
+:class:`Plan` is a convenience wrapper that allocates outputs as torch tensors on the current
+device and calls the same entry points.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpin.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1305_1505_amd.build`")
+lib = ctypes.CDLL(LIB_PATH)
+
+PIN_OK = 0
+PIN_ERR_INVALID_ARG = 1
+PIN_ERR_UNSUPPORTED_SIZE = 2
+PIN_ERR_OUT_OF_MEMORY = 3
+PIN_ERR_DEVICE = 4
+PIN_ERR_NOT_READY = 5
+PIN_ERR_BUDGET = 6
+PIN_ERR_CANCELLED = 7
+PIN_ERR_SHUTDOWN = 8
+PIN_ERR_TIMEOUT = 9
+
+PIN_FP32 = 0
+PIN_FP64 = 1
+NEVER = 255
+
+
+class pin_plan_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("box", ctypes.c_double), ("n_radii", ctypes.c_int),
+                ("radii_cells", ctypes.POINTER(ctypes.c_double)), ("sigma8", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("ns", ctypes.c_double), ("prec", ctypes.c_int)]
+
+
+class PinError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{lib.pin_status_string(status).decode()} ({status}): {message}")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_sig = {
+    "pin_size_supported": (ctypes.c_int, [ctypes.c_int]),
+    "pin_plan_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "pin_plan_validate": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc)]),
+    "pin_plan_create": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(_vp)]),
+    "pin_plan_destroy": (ctypes.c_int, [_vp]),
+    "pin_generate_field": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _vp]),
+    "pin_collapse_reset": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pin_collapse_times_range": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "pin_collapse_times": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pin_deformation_tensor": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
+    "pin_displacements": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pin_kernel_class_count": (ctypes.c_int, []),
+    "pin_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "pin_plan_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pin_plan_kernel_time": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_longlong)]),
+    "pin_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pin_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(status):
+    if status != PIN_OK:
+        raise PinError(status, lib.pin_last_error().decode())
+
+
+def make_desc(n, box, radii_cells, sigma8=0.8, gamma=0.21, ns=1.0, prec=PIN_FP32):
+    """A pin_plan_desc; the returned object keeps the radii array alive."""
+    radii = (ctypes.c_double * len(radii_cells))(*[float(r) for r in radii_cells])
+    d = pin_plan_desc(int(n), float(box), len(radii_cells), radii, float(sigma8), float(gamma), float(ns), int(prec))
+    d._radii = radii
+    return d
+
+
+def pin_size_supported(n):
+    return bool(lib.pin_size_supported(int(n)))
+
+
+def pin_plan_validate(desc):
+    _check(lib.pin_plan_validate(ctypes.byref(desc)))
+
+
+def pin_plan_workspace_bytes(desc):
+    out = ctypes.c_size_t(0)
+    _check(lib.pin_plan_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def pin_plan_create(desc):
+    h = _vp()
+    _check(lib.pin_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def pin_plan_destroy(plan):
+    _check(lib.pin_plan_destroy(plan))
+
+
+def pin_generate_field(plan, seed, dk, stream=0):
+    _check(lib.pin_generate_field(plan, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), _vp(dk), _vp(stream)))
+
+
+def pin_collapse_reset(plan, F, ridx, stream=0):
+    _check(lib.pin_collapse_reset(plan, _vp(F), _vp(ridx), _vp(stream)))
+
+
+def pin_collapse_times_range(plan, dk, F, ridx, r_begin, r_end, stream=0):
+    _check(lib.pin_collapse_times_range(plan, _vp(dk), _vp(F), _vp(ridx), int(r_begin), int(r_end), _vp(stream)))
+
+
+def pin_collapse_times(plan, dk, F, ridx, stream=0):
+    _check(lib.pin_collapse_times(plan, _vp(dk), _vp(F), _vp(ridx), _vp(stream)))
+
+
+def pin_deformation_tensor(plan, dk, r, T6, stream=0):
+    _check(lib.pin_deformation_tensor(plan, _vp(dk), int(r), _vp(T6), _vp(stream)))
+
+
+def pin_displacements(plan, dk, psi1, psi2, stream=0):
+    _check(lib.pin_displacements(plan, _vp(dk), _vp(psi1 or None), _vp(psi2 or None), _vp(stream)))
+
+
+def pin_kernel_class_count():
+    return lib.pin_kernel_class_count()
+
+
+def pin_kernel_class_name(cls):
+    return lib.pin_kernel_class_name(int(cls)).decode()
+
+
+def pin_plan_set_timing(plan, enable):
+    _check(lib.pin_plan_set_timing(plan, 1 if enable else 0))
+
+
+def pin_plan_kernel_time(plan, cls):
+    ms = ctypes.c_double(0)
+    cnt = ctypes.c_longlong(0)
+    _check(lib.pin_plan_kernel_time(plan, int(cls), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def pin_status_string(status):
+    return lib.pin_status_string(int(status)).decode()
+
+
+def pin_last_error():
+    return lib.pin_last_error().decode()
+
+
+class Plan:
+    """A plan with torch-tensor conveniences (outputs allocated on the current HIP device)."""
+
+    def __init__(self, n, box, radii_cells, sigma8=0.8, gamma=0.21, ns=1.0, prec=PIN_FP32):
+        import torch
+
+        self.torch = torch
+        self.n = int(n)
+        self.box = float(box)
+        self.radii = [float(r) for r in radii_cells]
+        self.prec = prec
+        self.desc = make_desc(n, box, radii_cells, sigma8, gamma, ns, prec)
+        self.handle = pin_plan_create(self.desc)
+        self.real = torch.float64 if prec == PIN_FP64 else torch.float32
+        self.cplx = torch.complex128 if prec == PIN_FP64 else torch.complex64
+
+    def close(self):
+        if self.handle is not None:
+            pin_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def empty_spectrum(self):
+        n = self.n
+        return self.torch.empty((n, n, n // 2 + 1), dtype=self.cplx, device="cuda")
+
+    def generate_field(self, seed, dk=None):
+        dk = self.empty_spectrum() if dk is None else dk
+        pin_generate_field(self.handle, seed, dk.data_ptr(), self._stream())
+        return dk
+
+    def _as_spectrum(self, dk):
+        if dk.dtype != self.cplx or not dk.is_cuda or not dk.is_contiguous():
+            raise TypeError(f"dk must be a contiguous {self.cplx} CUDA tensor")
+        if tuple(dk.shape) != (self.n, self.n, self.n // 2 + 1):
+            raise ValueError("dk has the wrong shape")
+        return dk
+
+    def collapse_times(self, dk, F=None, ridx=None):
+        n = self.n
+        dk = self._as_spectrum(dk)
+        F = self.torch.empty((n, n, n), dtype=self.real, device="cuda") if F is None else F
+        ridx = self.torch.empty((n, n, n), dtype=self.torch.uint8, device="cuda") if ridx is None else ridx
+        pin_collapse_times(self.handle, dk.data_ptr(), F.data_ptr(), ridx.data_ptr(), self._stream())
+        return F, ridx
+
+    def collapse_reset(self, F, ridx):
+        pin_collapse_reset(self.handle, F.data_ptr(), ridx.data_ptr(), self._stream())
+
+    def collapse_times_range(self, dk, F, ridx, r_begin, r_end):
+        dk = self._as_spectrum(dk)
+        pin_collapse_times_range(self.handle, dk.data_ptr(), F.data_ptr(), ridx.data_ptr(), r_begin, r_end,
+                                 self._stream())
+        return F, ridx
+
+    def deformation_tensor(self, dk, r):
+        n = self.n
+        dk = self._as_spectrum(dk)
+        T6 = self.torch.empty((6, n, n, n), dtype=self.real, device="cuda")
+        pin_deformation_tensor(self.handle, dk.data_ptr(), r, T6.data_ptr(), self._stream())
+        return T6
+
+    def displacements(self, dk, want_psi1=True, want_psi2=True):
+        n = self.n
+        dk = self._as_spectrum(dk)
+        p1 = self.torch.empty((3, n, n, n), dtype=self.real, device="cuda") if want_psi1 else None
+        p2 = self.torch.empty((3, n, n, n), dtype=self.real, device="cuda") if want_psi2 else None
+        pin_displacements(self.handle, dk.data_ptr(), p1.data_ptr() if p1 is not None else 0,
+                          p2.data_ptr() if p2 is not None else 0, self._stream())
+        return p1, p2

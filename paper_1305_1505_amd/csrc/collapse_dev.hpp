@@ -1,0 +1,146 @@
+// Per-point ellipsoidal collapse on the device (section "Collapse times", eq. F).
+//
+// The paper describes but does not print its collapse formula.  This file implements the reading
+// used throughout the library (truncated 3rd-order LPT along the first axis with a
+// quasi-spherical correction):
+//
+//   lambda_1 = largest eigenvalue of T, delta = tr T, mu2 = sum_{i<j} lambda_i lambda_j,
+//   mu3 = det T.  The first axis crosses orbits at the smallest D > 0 with
+//       J1(D) = 1 - lambda_1 D - (mu2/7) D^2 + (mu3/9 - 10 delta mu2/189) D^3 = 0,
+//   (2nd- and 3rd-order LPT traces shared equally by the three axes), i.e. at the largest
+//   positive root F_E3 of the monic cubic in F = 1/D
+//       P(F) = F^3 - lambda_1 F^2 - (mu2/7) F + (mu3/9 - 10 delta mu2/189),
+//   F_E3 = 0 if there is none.  Correction for near-spherical peaks:
+//       F = F_E3 * (1 + (X3/delta_c - 1) * s),  s = clamp(1 - 3p/delta, 0, 1) (delta > 0; else 0),
+//   p = sqrt(tr(B^2)/6), B = T - (delta/3) I, X3 = 2.05008... the root of the 3rd-order EdS
+//   sphere series 1 - x/3 - x^2/21 - 23x^3/1701, delta_c = (3/20)(12 pi)^(2/3).  A sphere gets
+//   F = delta/delta_c and a plane F = lambda_1.
+//
+// Arithmetic: float64.  lambda_1 from the trigonometric closed form of a symmetric 3x3
+// eigenproblem, lambda_1 = m + 2p cos(acos(r)/3) with r = det(B)/(2p^3); near r = -1
+// (lambda_1 ~ lambda_2) that form amplifies the rounding of r by 1/sqrt(1+r), so there the
+// eigenvalue comes from cyclic Jacobi rotations instead.  The cubic's largest real root comes from
+// the closed form (trigonometric for three real roots, Cardano otherwise) polished by Newton
+// steps on P.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pin {
+
+struct CollapseConst {
+  // X3 / delta_c - 1, with X3 and delta_c as above (both computed on the host in float64 and
+  // passed in, so the constants live in one place).
+  double sphere_gain;
+};
+
+__device__ __forceinline__ double cubic_largest_real_root(double a, double b, double c) {
+  // depressed cubic t^3 + p t + q with F = t - a/3
+  const double a3 = a * (1.0 / 3.0);
+  const double p = b - a * a3;
+  const double q = c - a3 * b + 2.0 * a3 * a3 * a3;
+  const double hq = 0.5 * q;
+  const double p3 = p * (1.0 / 3.0);
+  const double disc = hq * hq + p3 * p3 * p3;
+  double t;
+  if (disc < 0.0) {
+    // three real roots (p < 0): t_k = 2 r cos(theta/3 - 2 pi k/3), cos(theta) = -hq / r^3
+    const double r = sqrt(-p3);
+    double cth = -hq / (r * r * r);
+    cth = fmin(1.0, fmax(-1.0, cth));
+    t = 2.0 * r * cos(acos(cth) * (1.0 / 3.0));
+  } else {
+    const double u = cbrt(-hq - copysign(sqrt(disc), hq));
+    t = (u != 0.0) ? (u - p3 / u) : 0.0;
+  }
+  double x = t - a3;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double f = ((x + a) * x + b) * x + c;
+    const double fp = (3.0 * x + 2.0 * a) * x + b;
+    if (fp > 0.0) x -= f / fp;
+  }
+  return x;
+}
+
+// Largest eigenvalue of a symmetric 3x3 matrix by cyclic Jacobi rotations (each rotation zeroes
+// one off-diagonal element; the eigenvalues are the diagonal once all three are negligible).
+__device__ __noinline__ double jacobi_largest_eigenvalue(double a00, double a01, double a02, double a11,
+                                                         double a12, double a22) {
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = a01 * a01 + a02 * a02 + a12 * a12;
+    const double diag = a00 * a00 + a11 * a11 + a22 * a22;
+    if (off <= 1e-34 * diag || off == 0.0) break;
+    // rotation in the (0,1) plane
+    if (a01 != 0.0) {
+      const double th = (a11 - a00) / (2.0 * a01);
+      const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      a00 -= t * a01;
+      a11 += t * a01;
+      a01 = 0.0;
+      const double g = a02, h = a12;
+      a02 = c * g - s * h;
+      a12 = s * g + c * h;
+    }
+    // (0,2)
+    if (a02 != 0.0) {
+      const double th = (a22 - a00) / (2.0 * a02);
+      const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      a00 -= t * a02;
+      a22 += t * a02;
+      a02 = 0.0;
+      const double g = a01, h = a12;
+      a01 = c * g - s * h;
+      a12 = s * g + c * h;
+    }
+    // (1,2)
+    if (a12 != 0.0) {
+      const double th = (a22 - a11) / (2.0 * a12);
+      const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      a11 -= t * a12;
+      a22 += t * a12;
+      a12 = 0.0;
+      const double g = a01, h = a02;
+      a01 = c * g - s * h;
+      a02 = s * g + c * h;
+    }
+  }
+  return fmax(a00, fmax(a11, a22));
+}
+
+// Inverse collapse time F of one point from its six tensor components (float64).
+__device__ __forceinline__ double collapse_point(double xx, double xy, double xz, double yy, double yz,
+                                                 double zz, const CollapseConst& cc) {
+  const double delta = xx + yy + zz;
+  const double m = delta * (1.0 / 3.0);
+  const double mu2 = xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz;
+  const double mu3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+  const double bxx = xx - m, byy = yy - m, bzz = zz - m;
+  const double off = xy * xy + xz * xz + yz * yz;
+  const double p2 = (bxx * bxx + byy * byy + bzz * bzz + 2.0 * off) * (1.0 / 6.0);
+  const double p = sqrt(p2);
+  double l1 = m;
+  if (p2 > 0.0) {
+    const double detb = bxx * (byy * bzz - yz * yz) - xy * (xy * bzz - yz * xz) + xz * (xy * yz - byy * xz);
+    double r = detb / (2.0 * p2 * p);
+    r = fmin(1.0, fmax(-1.0, r));
+    if (r > -1.0 + 1e-8) {
+      l1 = m + 2.0 * p * cos(acos(r) * (1.0 / 3.0));
+    } else {
+      l1 = jacobi_largest_eigenvalue(xx, xy, xz, yy, yz, zz);
+    }
+  }
+  const double ca = -l1;
+  const double cb = -mu2 * (1.0 / 7.0);
+  const double cc0 = mu3 * (1.0 / 9.0) - 10.0 * delta * mu2 * (1.0 / 189.0);
+  const double root = cubic_largest_real_root(ca, cb, cc0);
+  const double fe3 = root > 0.0 ? root : 0.0;
+  double s = 0.0;
+  if (delta > 0.0) s = fmin(1.0, fmax(0.0, 1.0 - 3.0 * p / delta));
+  return fe3 * (1.0 + cc.sphere_gain * s);
+}
+
+}  // namespace pin

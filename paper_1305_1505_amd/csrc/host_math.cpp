@@ -1,0 +1,119 @@
+// Host-side float64 tables and constants (spectrum normalisation, twiddles, windows).
+#include "host_math.hpp"
+
+#include <cmath>
+
+namespace pin {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// 16-point Gauss-Legendre nodes and weights on [-1, 1], by Newton iteration on P_16.
+struct GaussLegendre {
+  double x[16], w[16];
+  GaussLegendre() {
+    const int n = 16;
+    for (int i = 0; i < n; ++i) {
+      double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+          const double p2 = p1;
+          p1 = p0;
+          p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+        }
+        const double dp = n * (z * p0 - p1) / (z * z - 1.0);
+        const double dz = p0 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-16) {
+          double q0 = 1.0, q1 = 0.0;
+          for (int j = 1; j <= n; ++j) {
+            const double q2 = q1;
+            q1 = q0;
+            q0 = ((2.0 * j - 1.0) * z * q1 - (j - 1.0) * q2) / j;
+          }
+          const double dq = n * (z * q0 - q1) / (z * z - 1.0);
+          x[i] = z;
+          w[i] = 2.0 / ((1.0 - z * z) * dq * dq);
+          break;
+        }
+      }
+    }
+  }
+};
+
+}  // namespace
+
+double bbks_transfer(double k, double gamma) {
+  const double q = k / gamma;
+  const double x = 2.34 * q;
+  const double lead = x > 1e-8 ? std::log1p(x) / x : 1.0 - 0.5 * x;
+  const double poly = 1.0 + 3.89 * q + std::pow(16.1 * q, 2) + std::pow(5.46 * q, 3) + std::pow(6.71 * q, 4);
+  return lead * std::pow(poly, -0.25);
+}
+
+double tophat_window(double x) {
+  if (std::fabs(x) < 1e-3) return 1.0 - x * x / 10.0 + x * x * x * x / 280.0;
+  return 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+}
+
+double sigma2_tophat_unit(double radius, double gamma, double ns) {
+  static const GaussLegendre gl;
+  const double a = std::log(1e-7), b = std::log(1e3);
+  const int panels = 4000;
+  const double h = (b - a) / panels;
+  double total = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double mid = a + (p + 0.5) * h;
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) {
+      const double lnk = mid + 0.5 * h * gl.x[i];
+      const double k = std::exp(lnk);
+      const double t = bbks_transfer(k, gamma);
+      const double w = tophat_window(k * radius);
+      s += gl.w[i] * k * k * k * std::pow(k, ns) * t * t * w * w;
+    }
+    total += 0.5 * h * s;
+  }
+  return total / (2.0 * kPi * kPi);
+}
+
+double amplitude_for_sigma8(double sigma8, double gamma, double ns) {
+  return sigma8 * sigma8 / sigma2_tophat_unit(8.0, gamma, ns);
+}
+
+double eds_sphere_root() {
+  auto f = [](double x) { return 1.0 - x / 3.0 - x * x / 21.0 - 23.0 * x * x * x / 1701.0; };
+  double lo = 1.0, hi = 3.0;   // f(1) > 0 > f(3)
+  for (int i = 0; i < 200; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (f(mid) > 0.0) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double eds_delta_c() { return 0.15 * std::pow(12.0 * kPi, 2.0 / 3.0); }
+
+std::vector<double> twiddles(int n) {
+  std::vector<double> t(2 * (size_t)n);
+  for (int m = 0; m < n; ++m) {
+    // angle in extended precision, then rounded once to float64
+    const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+    t[2 * m] = (double)std::cos(ang);
+    t[2 * m + 1] = (double)std::sin(ang);
+  }
+  return t;
+}
+
+std::vector<double> gaussian_window_table(int n, double radius_cells) {
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) {
+    const double f = i < n / 2 ? i : i - n;
+    const double kr = 2.0 * kPi * f * radius_cells / n;
+    w[i] = std::exp(-0.5 * kr * kr);
+  }
+  return w;
+}
+
+}  // namespace pin

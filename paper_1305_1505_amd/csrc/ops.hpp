@@ -1,0 +1,42 @@
+// Host-side table of the kernel launchers for one (precision, N).  Each supported pair is
+// instantiated in its own translation unit (inst.hip compiled with PIN_INST_N / PIN_INST_FP64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pin {
+
+struct LaunchShape {
+  int grid;
+  int block;
+};
+
+struct SizeOps {
+  int n;
+  bool fp64;
+  // x pass from the user half spectrum.  mode 0: Hessian (3 outputs, window table or null);
+  // mode 1: gradient (2 outputs).  out = first workspace slot of the outputs.
+  void (*xpass)(int mode, const void* dk, void* out, const void* wtab, const void* tw, double scale,
+                hipStream_t s);
+  // fused forward-x / inverse-x (2LPT): one input slot -> two output slots
+  void (*xpass_fwdinv)(const void* in, void* out, const void* tw, double scale, hipStream_t s);
+  // y pass: recipe 0 Hessian (3 -> 6), 1 gradient (2 -> 3), 2 forward (1 -> 1)
+  void (*ypass)(int recipe, const void* in, void* out, const void* tw, hipStream_t s);
+  // z pass with the collapse epilogue at radius index r
+  void (*zpass_collapse)(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain,
+                         hipStream_t s);
+  // z pass storing nc = 6 (Hessian) or 3 (gradient) real components to out[nc][N^3]
+  void (*zpass_store)(int nc, const void* in, const void* tw, void* out, hipStream_t s);
+  // z pass computing the 2LPT source and its forward transform along z into one slot
+  void (*zpass_mu2)(const void* in, const void* tw, void* out_slot, hipStream_t s);
+  void (*grf)(void* dk, uint64_t seed, double norm, double kf, double gamma, double ns, hipStream_t s);
+  void (*reset)(void* F, uint8_t* ridx, hipStream_t s);
+  // launch shapes, for reports
+  LaunchShape shape_x, shape_y, shape_z;
+};
+
+const SizeOps* find_ops(int n, bool fp64);
+
+}  // namespace pin
