@@ -64,7 +64,8 @@ typedef struct pin_plan_s* pin_plan;
 
 /* Problem description (section "Collapse times"): grid, box, radii and spectrum. */
 typedef struct {
-  int n;                     /* grid points per side; even, of the form 2^a 3^b, 8..1536     */
+  int n;                     /* grid points per side: 8, 12, 16, 24, 32, 48, 64, 96, 128,
+                                192, 256, 384, 512, 768 or 1024 (pin_size_supported)         */
   double box;                /* side L in Mpc/h, > 0                                          */
   int n_radii;               /* 1..254                                                        */
   const double* radii_cells; /* host array of n_radii radii in cells, > 0, strictly decreasing
@@ -127,6 +128,17 @@ pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6
  * transform (k = 0 and Nyquist modes zeroed).  Either output may be NULL to skip it. */
 pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* psi2,
                              hipStream_t stream);
+
+/* eq. F per point: the inverse collapse time of the ellipsoidal collapse model (the per-point
+ * step of pin_collapse_times) for caller-given tensors.  T6 (device, [6][count] of the plan's
+ * real type, components xx, xy, xz, yy, yz, zz) -> F (device, [count]).  Model: lambda_1 = the
+ * largest eigenvalue, delta = tr T, mu2 = sum_{i<j} lambda_i lambda_j, mu3 = det T; F_E3 = the
+ * largest positive root of F^3 - lambda_1 F^2 - (mu2/7) F + (mu3/9 - 10 delta mu2/189) (0 if
+ * none), the first-axis orbit crossing of 3rd-order LPT with the higher-order traces shared
+ * equally by the axes; F = F_E3 (1 + (X3/delta_c - 1) s) with s = clamp(1 - 3p/delta, 0, 1) for
+ * delta > 0 (else 0), p^2 = tr((T - delta/3)^2)/6, X3 = 2.05008... the root of
+ * 1 - x/3 - x^2/21 - 23x^3/1701, delta_c = (3/20)(12 pi)^(2/3).  count = 0 is a no-op. */
+pin_status pin_inverse_collapse_time(pin_plan plan, const void* T6, size_t count, void* F, hipStream_t stream);
 
 /* Per-kernel timing with HIP events recorded around every launch of the plan on its stream.
  * Kernel classes are numbered 0..pin_kernel_class_count()-1 and named by pin_kernel_class_name. */

@@ -60,6 +60,7 @@ _sig = {
     "pin_collapse_times": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pin_deformation_tensor": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "pin_displacements": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
     "pin_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int]),
     "pin_plan_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -133,6 +134,10 @@ def pin_deformation_tensor(plan, dk, r, T6, stream=0):
 
 def pin_displacements(plan, dk, psi1, psi2, stream=0):
     _check(lib.pin_displacements(plan, _vp(dk), _vp(psi1 or None), _vp(psi2 or None), _vp(stream)))
+
+
+def pin_inverse_collapse_time(plan, T6, count, F, stream=0):
+    _check(lib.pin_inverse_collapse_time(plan, _vp(T6), ctypes.c_size_t(int(count)), _vp(F), _vp(stream)))
 
 
 def pin_kernel_class_count():
@@ -231,6 +236,14 @@ class Plan:
         T6 = self.torch.empty((6, n, n, n), dtype=self.real, device="cuda")
         pin_deformation_tensor(self.handle, dk.data_ptr(), r, T6.data_ptr(), self._stream())
         return T6
+
+    def inverse_collapse_time(self, t6):
+        """F for a (6, count) tensor array (any float dtype; converted to the plan's precision)."""
+        t6 = self.torch.as_tensor(t6).to(device="cuda", dtype=self.real).contiguous()
+        count = t6.shape[1]
+        F = self.torch.empty((count,), dtype=self.real, device="cuda")
+        pin_inverse_collapse_time(self.handle, t6.data_ptr(), count, F.data_ptr(), self._stream())
+        return F
 
     def displacements(self, dk, want_psi1=True, want_psi2=True):
         n = self.n

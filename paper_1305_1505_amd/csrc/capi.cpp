@@ -9,7 +9,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/pin.h"
+#include "pin.h"
 #include "host_math.hpp"
 #include "ops.hpp"
 
@@ -42,12 +42,15 @@ enum KernelClass {
   KC_ZPASS_MU2,
   KC_YPASS_FWD,
   KC_XPASS_FWDINV,
+  KC_COLLAPSE_POINTS,
+  KC_PREP,
   KC_COUNT
 };
 
 const char* const kClassNames[KC_COUNT] = {
     "grf",         "reset",       "xpass_hessian", "ypass_hessian", "zpass_collapse", "zpass_store",
-    "xpass_gradient", "ypass_gradient", "zpass_mu2", "ypass_forward", "xpass_fwdinv"};
+    "xpass_gradient", "ypass_gradient", "zpass_mu2", "ypass_forward", "xpass_fwdinv",
+    "collapse_points", "prep"};
 
 }  // namespace
 
@@ -64,8 +67,9 @@ struct pin_plan_s {
   int device = 0;
   void* tw = nullptr;
   void* wtab = nullptr;
-  void* X = nullptr;      // 3 workspace slots
-  void* Y = nullptr;      // 6 workspace slots
+  void* X = nullptr;      // 4 half slots (= 2 packed slots)
+  void* Y = nullptr;      // 6 half slots (= 3 packed slots)
+  void* G = nullptr;      // 1 half slot: the radius-independent Hessian input
   size_t slot_bytes = 0;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[KC_COUNT];
@@ -140,7 +144,7 @@ void validate_desc(const pin_plan_desc* d) {
 size_t workspace_bytes(const pin_plan_desc* d) {
   const size_t rb = d->prec == PIN_FP64 ? 8 : 4;
   const size_t slot = (size_t)d->n * d->n * (d->n / 2) * 2 * rb;
-  return 9 * slot + (size_t)d->n * 2 * rb + (size_t)d->n * d->n_radii * rb;
+  return 11 * slot + (size_t)d->n * 2 * rb + (size_t)d->n * d->n_radii * rb;
 }
 
 // Check that [p, p + bytes) lies inside one device allocation of the plan's device.
@@ -214,14 +218,20 @@ void free_plan(pin_plan p) {
   if (p->wtab) (void)hipFree(p->wtab);
   if (p->X) (void)hipFree(p->X);
   if (p->Y) (void)hipFree(p->Y);
+  if (p->G) (void)hipFree(p->G);
   delete p;
 }
 
-void run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, int r1, hipStream_t s) {
+void prep_hessian_input(pin_plan p, const void* dk, hipStream_t s) {
   const double scale = 1.0 / ((double)p->n * p->n * p->n);
+  p->launch(KC_PREP, s, [&] { p->ops->prep(dk, p->G, scale, s); });
+}
+
+void run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, int r1, hipStream_t s) {
+  prep_hessian_input(p, dk, s);
   for (int r = r0; r < r1; ++r) {
     const char* w = static_cast<const char*>(p->wtab) + (size_t)r * p->n * p->real_bytes;
-    p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, dk, p->X, w, p->tw, scale, s); });
+    p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
     p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
     p->launch(KC_ZPASS_COLLAPSE, s, [&] { p->ops->zpass_collapse(p->Y, p->tw, F, ridx, r, p->sphere_gain, s); });
   }
@@ -267,8 +277,9 @@ pin_status pin_plan_create(const pin_plan_desc* desc, pin_plan* out) {
     p->slot_bytes = (size_t)p->n * p->n * (p->n / 2) * p->complex_bytes();
     p->tw = device_alloc((size_t)p->n * p->complex_bytes(), "twiddles");
     p->wtab = device_alloc((size_t)p->n * p->nr * p->real_bytes, "windows");
-    p->X = device_alloc(3 * p->slot_bytes, "workspace X");
+    p->X = device_alloc(4 * p->slot_bytes, "workspace X");
     p->Y = device_alloc(6 * p->slot_bytes, "workspace Y");
+    p->G = device_alloc(p->slot_bytes, "workspace G");
     upload(p->tw, pin::twiddles(p->n), p->fp64);
     std::vector<double> w;
     w.reserve((size_t)p->n * p->nr);
@@ -341,9 +352,9 @@ pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6
     if (r < -1 || r >= plan->nr) fail(PIN_ERR_INVALID_ARG, "radius index must be -1 or in [0, n_radii)");
     check_device_range(dk, plan->half_spectrum_bytes(), "dk");
     check_device_range(T6, 6 * plan->real_field_bytes(), "T6");
-    const double scale = 1.0 / ((double)plan->n * plan->n * plan->n);
     const void* w = r < 0 ? nullptr : static_cast<const char*>(plan->wtab) + (size_t)r * plan->n * plan->real_bytes;
-    plan->launch(KC_XPASS_HESS, stream, [&] { plan->ops->xpass(0, dk, plan->X, w, plan->tw, scale, stream); });
+    prep_hessian_input(plan, dk, stream);
+    plan->launch(KC_XPASS_HESS, stream, [&] { plan->ops->xpass(0, plan->G, plan->X, w, plan->tw, 1.0, stream); });
     plan->launch(KC_YPASS_HESS, stream, [&] { plan->ops->ypass(0, plan->X, plan->Y, plan->tw, stream); });
     plan->launch(KC_ZPASS_STORE, stream, [&] { plan->ops->zpass_store(6, plan->Y, plan->tw, T6, stream); });
   });
@@ -369,7 +380,8 @@ pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* ps
     if (psi2) {
       // mu2 of the unsmoothed tensor, forward along z (fused), y, x; then (3/7) i (L/2pi) f / f^2
       // and the inverse gradient transforms.
-      p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, dk, p->X, nullptr, p->tw, 1.0 / n3, s); });
+      prep_hessian_input(p, dk, s);
+      p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, nullptr, p->tw, 1.0, s); });
       p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
       p->launch(KC_ZPASS_MU2, s, [&] { p->ops->zpass_mu2(p->Y, p->tw, p->xslot(0), s); });
       p->launch(KC_YPASS_FWD, s, [&] { p->ops->ypass(2, p->xslot(0), p->xslot(1), p->tw, s); });
@@ -378,6 +390,18 @@ pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* ps
       p->launch(KC_YPASS_GRAD, s, [&] { p->ops->ypass(1, p->Y, p->X, p->tw, s); });
       p->launch(KC_ZPASS_STORE, s, [&] { p->ops->zpass_store(3, p->X, p->tw, psi2, s); });
     }
+  });
+}
+
+pin_status pin_inverse_collapse_time(pin_plan plan, const void* T6, size_t count, void* F, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (count == 0) return;
+    if (count > ((size_t)1 << 40)) fail(PIN_ERR_INVALID_ARG, "count is too large");
+    check_device_range(T6, 6 * count * plan->real_bytes, "T6");
+    check_device_range(F, count * plan->real_bytes, "F");
+    plan->launch(KC_COLLAPSE_POINTS, stream,
+                 [&] { plan->ops->collapse_points(T6, count, F, plan->sphere_gain, stream); });
   });
 }
 

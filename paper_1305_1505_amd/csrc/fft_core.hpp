@@ -5,8 +5,9 @@
 //   interleaved (IL = true):  element n of pencil p of transform q at (q*N + n)*P + p -- the
 //       pencil index runs fastest, matching a strided global tile whose P pencils are P
 //       consecutive (contiguous) z positions;
-//   contiguous  (IL = false): at (q*P + p)*N + n -- the element index runs fastest, matching a
-//       global tile of P contiguous lines.
+//   contiguous  (IL = false): at (q*P + p)*NPAD + n + n/16 -- the element index runs fastest,
+//       matching a global tile of P contiguous lines; one pad element per 16 spreads the
+//       stride-R accesses of the Stockham writes over the LDS banks.
 // The first stage reads its inputs from registers (loaded from HBM by the caller, with any
 // spectral multiplier already applied) and the last stage leaves its outputs in registers, in
 // the same per-thread layout: thread t owns butterflies b = t + k*T (k < K0) of the first
@@ -177,10 +178,11 @@ struct Engine {
   static constexpr int nb(int R) { return Q * P * (N / R); }
   static constexpr int kcount(int R) { return (nb(R) + T - 1) / T; }
   static constexpr int K0 = kcount(R0);
-  static constexpr int LDS_ELEMS = Q * P * N;
+  static constexpr int NPAD = IL ? N : N + N / 16 + 1;
+  static constexpr int LDS_ELEMS = Q * P * NPAD;
 
   __device__ static __forceinline__ int lds_index(int q, int p, int n) {
-    return IL ? (q * N + n) * P + p : (q * P + p) * N + n;
+    return IL ? (q * N + n) * P + p : (q * P + p) * NPAD + n + (n >> 4);
   }
 
   // butterfly b of a radix-R stage -> (q, p, j)

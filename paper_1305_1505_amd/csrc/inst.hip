@@ -19,66 +19,78 @@ using RR = std::conditional_t<PIN_INST_FP64 != 0, double, float>;
 using VV = Cplx<RR>::type;
 static_assert(size_ok(NN) && NN % 2 == 0, "grid size");
 
+void prep(const void* dk, void* g0, double scale, hipStream_t s) {
+  const size_t total = (size_t)NN * NN * (NN / 2);
+  const int block = 256;
+  const int grid = (int)((total + block - 1) / block);
+  hipLaunchKernelGGL((k_prep<RR, NN>), dim3(grid), dim3(block), 0, s, static_cast<const VV*>(dk),
+                     static_cast<VV*>(g0), (RR)scale);
+}
+
 void xpass(int mode, const void* dk, void* out, const void* wtab, const void* tw, double scale, hipStream_t s) {
+  using S = Strided<RR, NN, +1>;
   if (mode == 0) {
-    using X = XPass<RR, NN, 0>;
-    hipLaunchKernelGGL((k_xpass<RR, NN, 0>), dim3(X::GRID), dim3(X::T), 0, s, static_cast<const VV*>(dk),
+    hipLaunchKernelGGL((k_xpass<RR, NN, 0>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(dk),
                        static_cast<VV*>(out), static_cast<const RR*>(wtab), static_cast<const VV*>(tw), (RR)scale);
   } else {
-    using X = XPass<RR, NN, 1>;
-    hipLaunchKernelGGL((k_xpass<RR, NN, 1>), dim3(X::GRID), dim3(X::T), 0, s, static_cast<const VV*>(dk),
+    hipLaunchKernelGGL((k_xpass<RR, NN, 1>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(dk),
                        static_cast<VV*>(out), static_cast<const RR*>(nullptr), static_cast<const VV*>(tw), (RR)scale);
   }
 }
 
 void xpass_fwdinv(const void* in, void* out, const void* tw, double scale, hipStream_t s) {
-  using X = XPass<RR, NN, 1>;
-  hipLaunchKernelGGL((k_xpass_fwdinv<RR, NN>), dim3(X::GRID), dim3(X::T), 0, s, static_cast<const VV*>(in),
+  using S = Strided<RR, NN, +1>;
+  hipLaunchKernelGGL((k_xpass_fwdinv<RR, NN>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
                      static_cast<VV*>(out), static_cast<const VV*>(tw), (RR)scale);
 }
 
-template <int RECIPE> void ypass_r(const void* in, void* out, const void* tw, hipStream_t s) {
-  using Y = YPass<RR, NN, RECIPE>;
-  hipLaunchKernelGGL((k_ypass<RR, NN, RECIPE>), dim3(Y::GRID), dim3(Y::T), 0, s, static_cast<const VV*>(in),
-                     static_cast<VV*>(out), static_cast<const VV*>(tw));
-}
-
 void ypass(int recipe, const void* in, void* out, const void* tw, hipStream_t s) {
-  if (recipe == 0) ypass_r<0>(in, out, tw, s);
-  else if (recipe == 1) ypass_r<1>(in, out, tw, s);
-  else ypass_r<2>(in, out, tw, s);
+  if (recipe == 0) {
+    using S = Strided<RR, NN, +1>;
+    hipLaunchKernelGGL((k_ypass_packed<RR, NN, 0>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+  } else if (recipe == 1) {
+    using S = Strided<RR, NN, +1>;
+    hipLaunchKernelGGL((k_ypass_packed<RR, NN, 1>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+  } else {
+    using S = Strided<RR, NN, -1>;
+    hipLaunchKernelGGL((k_ypass_fwd<RR, NN>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+  }
 }
 
 void zpass_collapse(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain, hipStream_t s) {
-  using Z = ZPass<RR, NN, 6, EPI_COLLAPSE>;
+  using Z = ZPass<RR, NN, 3, EPI_COLLAPSE>;
   ZArgs a{};
   a.F = F;
   a.ridx = ridx;
   a.r = r;
   a.cc.sphere_gain = sphere_gain;
-  hipLaunchKernelGGL((k_zpass<RR, NN, 6, EPI_COLLAPSE>), dim3(Z::GRID), dim3(Z::T), 0, s,
+  hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_COLLAPSE>), dim3(Z::GRID), dim3(Z::T), 0, s,
                      static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
 }
 
 void zpass_store(int nc, const void* in, const void* tw, void* out, hipStream_t s) {
   ZArgs a{};
   a.out = out;
+  a.nc = nc;
   if (nc == 6) {
-    using Z = ZPass<RR, NN, 6, EPI_STORE>;
-    hipLaunchKernelGGL((k_zpass<RR, NN, 6, EPI_STORE>), dim3(Z::GRID), dim3(Z::T), 0, s,
-                       static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
-  } else {
     using Z = ZPass<RR, NN, 3, EPI_STORE>;
     hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_STORE>), dim3(Z::GRID), dim3(Z::T), 0, s,
+                       static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
+  } else {
+    using Z = ZPass<RR, NN, 2, EPI_STORE>;
+    hipLaunchKernelGGL((k_zpass<RR, NN, 2, EPI_STORE>), dim3(Z::GRID), dim3(Z::T), 0, s,
                        static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
   }
 }
 
 void zpass_mu2(const void* in, const void* tw, void* out_slot, hipStream_t s) {
-  using Z = ZPass<RR, NN, 6, EPI_MU2>;
+  using Z = ZPass<RR, NN, 3, EPI_MU2>;
   ZArgs a{};
   a.out = out_slot;
-  hipLaunchKernelGGL((k_zpass<RR, NN, 6, EPI_MU2>), dim3(Z::GRID), dim3(Z::T), 0, s,
+  hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_MU2>), dim3(Z::GRID), dim3(Z::T), 0, s,
                      static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
 }
 
@@ -97,6 +109,15 @@ void reset(void* F, uint8_t* ridx, hipStream_t s) {
   hipLaunchKernelGGL((k_reset<RR>), dim3(grid), dim3(block), 0, s, static_cast<RR*>(F), ridx, total);
 }
 
+void collapse_points(const void* t6, size_t count, void* F, double sphere_gain, hipStream_t s) {
+  if (count == 0) return;
+  CollapseConst cc{sphere_gain};
+  const int block = 256;
+  const int grid = (int)((count + block - 1) / block);
+  hipLaunchKernelGGL((k_collapse_points<RR>), dim3(grid), dim3(block), 0, s, static_cast<const RR*>(t6), count,
+                     static_cast<RR*>(F), cc);
+}
+
 }  // namespace
 
 #define PIN_CAT2(a, b, c) a##b##_##c
@@ -104,10 +125,10 @@ void reset(void* F, uint8_t* ridx, hipStream_t s) {
 
 const SizeOps* PIN_CAT(ops_, PIN_INST_FP64, PIN_INST_N)() {
   static const SizeOps ops = {
-      NN, PIN_INST_FP64 != 0, xpass, xpass_fwdinv, ypass, zpass_collapse, zpass_store, zpass_mu2, grf, reset,
-      LaunchShape{XPass<RR, NN, 0>::GRID, XPass<RR, NN, 0>::T},
-      LaunchShape{YPass<RR, NN, 0>::GRID, YPass<RR, NN, 0>::T},
-      LaunchShape{ZPass<RR, NN, 6, EPI_COLLAPSE>::GRID, ZPass<RR, NN, 6, EPI_COLLAPSE>::T}};
+      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, ypass, zpass_collapse, zpass_store, zpass_mu2, grf, reset, collapse_points,
+      LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
+      LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
+      LaunchShape{ZPass<RR, NN, 3, EPI_COLLAPSE>::GRID, ZPass<RR, NN, 3, EPI_COLLAPSE>::T}};
   return &ops;
 }
 

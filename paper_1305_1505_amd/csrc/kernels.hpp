@@ -1,20 +1,28 @@
 // HIP kernels of the collapse-time path for one grid size N and one precision.
 //
 // Layouts (C order, z fastest):
-//   user half spectrum dk      [N][N][N/2+1]   complex
-//   workspace slot             [N][N][N/2]     complex -- the kz = N/2 (Nyquist) plane is zero
-//                                                         by construction and is not stored
-//   real field                 [N][N][N]
+//   user half spectrum dk   [N][N][N/2+1] complex
+//   half slot               [N][N][N/2]   complex -- the kz = N/2 (Nyquist) plane is zero by
+//                                                    construction and is not stored
+//   packed z slot           [N][N][N]     complex -- for one pair of real outputs (A, B), the
+//       full-length z spectrum C = A + iB of each (x, y) line, stored as
+//         P[k]       = C[k]       k in [0, N/2)
+//         P[N/2 + k] = C[N - k]   k in [1, N/2)     (= conj(A[k]) + i conj(B[k]))
+//       (P[N/2], the Nyquist term, is zero and is neither written nor read), so that both halves
+//       are written as aligned runs by the y pass and the z pass loads each element once.
+//   real field              [N][N][N]
 //
 // Inverse 3D transform of the six Hessian components with shared prefixes.  With
 // g = M W dk / f^2 (M zeroes Nyquist modes, W the Gaussian window, f the integer wavevector),
 // component (a, b, c) with a + b + c = 2 is the inverse transform of fx^a fy^b fz^c g, and the
-// factors fx^a, fy^b commute with the later axes' transforms:
-//   x pass:  X_a  = IFFT_x[fx^a g]                    a = 0, 1, 2       (1 -> 3 arrays)
-//   y pass:  Y_ab = IFFT_y[fy^b X_a]                  (a, b) with a + b <= 2 (3 -> 6 arrays)
-//   z pass:  T_abc = C2R_z[fz^c Y_ab]                 6 real values per point, in registers,
-//            consumed by the per-point epilogue (collapse, store, or the 2LPT source).
+// factors fx^a, fy^b, fz^c commute with the other axes' transforms:
+//   x pass:  X_a = IFFT_x[fx^a g]                      a = 0, 1, 2         (1 -> 3 half slots)
+//   y pass:  S_abc = IFFT_y[fy^b X_a] fz^c, written in pairs of components (3 -> 3 packed slots)
+//   z pass:  IFFT_z of each packed pair gives two real components per complex transform; the six
+//            real values of a point stay in registers for the per-point epilogue (collapse,
+//            store, or the 2LPT source).
 // Gradients (displacements) use the same passes with a + b + c = 1 and g = i c M dk / f^2.
+// Every kernel copies the twiddle table to LDS first.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,27 +35,61 @@ namespace pin {
 
 // ---------------------------------------------------------------------------------------------
 // Tile shapes
+// Tuning constants (measured at 512^3 on MI355X): 128-byte z rows for the strided passes; the z
+// pass keeps one transform of 4 lines in LDS at a time (its three transforms run in turn), which
+// keeps its LDS below 25 KB so that VGPRs, not LDS, bound its occupancy.
+constexpr int kRowBytes = 128;
+constexpr bool kZSequential = true;
+constexpr int kZWaves = 4;
 template <typename R> struct Tile {
   using V = typename Cplx<R>::type;
-  static constexpr int PS = 128 / (int)sizeof(V);   // strided passes: 128-byte rows of z
+  static constexpr int PS = kRowBytes / (int)sizeof(V);   // strided passes: rows of z
 };
 
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b mod 8).  Strided tiles
+// 2m and 2m+1 share 128-byte lines when rows are 64 bytes; this maps them to blocks b and b+8,
+// which run on the same XCD one after the other, so the second read of each line hits its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  if (kRowBytes >= 128) return b;
+  const int full = nblocks & ~15;
+  if (b >= full) return b;
+  return (b & ~15) + ((b & 7) << 1) + ((b >> 3) & 1);
+}
+
 constexpr int round_up64(int x) { return (x + 63) / 64 * 64; }
-constexpr int strided_threads(int nb0) { return round_up64(nb0 < 512 ? nb0 : 512); }
+constexpr int strided_threads(int nb0) { return round_up64(nb0 < 1024 ? nb0 : 1024); }
 constexpr int pow2_floor(int x) {
   int p = 1;
   while (p * 2 <= x) p *= 2;
   return p;
 }
-// z pass: P lines per workgroup so that T = P * N/R0 threads (<= 256) and Q*P*N*sizeof(V) of LDS
+
+// Strided passes (x, y): a workgroup owns PS consecutive z (one 128-byte row) of one pencil set
+// and all N elements along the transform axis.
+template <typename R, int N, int DIR>
+struct Strided {
+  using V = typename Cplx<R>::type;
+  static constexpr int PS = Tile<R>::PS;
+  static constexpr int HZ = N / 2;
+  static constexpr int NZT = (HZ + PS - 1) / PS;
+  using E0 = Engine<V, N, PS, 1, true, 64, DIR>;
+  static constexpr int T = strided_threads(E0::nb(E0::R0));
+  using E = Engine<V, N, PS, 1, true, T, DIR>;
+  static constexpr int GRID = N * NZT;
+  static constexpr size_t HSLOT = (size_t)N * N * HZ;
+};
+
+// z pass: P lines per workgroup so that T = P * N/R0 threads (<= 64 kZWaves) and the LDS tile
 // stays within 96 KB.
 template <typename R, int N, int Q> struct ZTile {
   using V = typename Cplx<R>::type;
   static constexpr int R0 = factorize(N).r[0];
   static constexpr int M0 = N / R0;
-  static constexpr int P_by_threads = pow2_floor(256 / M0 > 0 ? 256 / M0 : 1);
-  static constexpr int P_by_lds = pow2_floor((96 * 1024) / (Q * N * (int)sizeof(V)) > 0
-                                                 ? (96 * 1024) / (Q * N * (int)sizeof(V)) : 1);
+  static constexpr int NPAD = N + N / 16 + 1;
+  static constexpr int QL = kZSequential ? 1 : Q;   // transforms resident in LDS at once
+  static constexpr int P_by_threads = pow2_floor((kZWaves * 64) / M0 > 0 ? (kZWaves * 64) / M0 : 1);
+  static constexpr int P_by_lds = pow2_floor((96 * 1024) / (QL * NPAD * (int)sizeof(V)) > 0
+                                                 ? (96 * 1024) / (QL * NPAD * (int)sizeof(V)) : 1);
   static constexpr int P0 = P_by_threads < P_by_lds ? P_by_threads : P_by_lds;
   static constexpr int P = P0 < 2 ? 2 : P0;   // even: the 2LPT epilogue pairs lines
   static constexpr int T = P * M0;
@@ -59,36 +101,58 @@ template <typename R> __device__ __forceinline__ R powf_int(R f, int e) {
   return e == 0 ? R(1) : (e == 1 ? f : f * f);
 }
 
-// ---------------------------------------------------------------------------------------------
-// x pass from the user half spectrum.  MODE 0 (Hessian): NA = 3 outputs, multiplier
-// W(x)W(y)W(z) scale / f^2 (wtab may be null: no smoothing).  MODE 1 (gradient): NA = 2,
-// multiplier i * scale / f^2.
-template <typename R, int N, int MODE>
-struct XPass {
-  using V = typename Cplx<R>::type;
-  static constexpr int PS = Tile<R>::PS;
-  static constexpr int HZ = N / 2;
-  static constexpr int NZT = (HZ + PS - 1) / PS;
-  static constexpr int NA = MODE == 0 ? 3 : 2;
-  using E0 = Engine<V, N, PS, 1, true, 64, +1>;
-  static constexpr int T = strided_threads(E0::nb(E0::R0));
-  using E = Engine<V, N, PS, 1, true, T, +1>;
-  static constexpr int GRID = N * NZT;
-};
+template <int N, int T, typename V>
+__device__ __forceinline__ void load_twiddles(V* __restrict__ s_tw, const V* __restrict__ tw, int t) {
+  for (int i = t; i < N; i += T) s_tw[i] = tw[i];
+  __syncthreads();
+}
 
+// ---------------------------------------------------------------------------------------------
+// Radius-independent part of the Hessian multiplier, once per call: g0 = M dk scale / f^2 into
+// a half slot whose rows are 128-byte aligned (the user spectrum's rows of N/2+1 complex are
+// not), so the per-radius x pass reads whole cache lines.
+template <typename R, int N>
+__global__ void k_prep(const typename Cplx<R>::type* __restrict__ dk, typename Cplx<R>::type* __restrict__ g0,
+                       R scale) {
+  using V = typename Cplx<R>::type;
+  constexpr int HZ = N / 2, NH = N / 2 + 1;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)N * N * HZ) return;
+  const int z = (int)(i % HZ);
+  const int y = (int)((i / HZ) % N);
+  const int x = (int)(i / ((size_t)HZ * N));
+  V out = V{R(0), R(0)};
+  if (x != N / 2 && y != N / 2) {
+    const int fx = ifreq(x, N), fy = ifreq(y, N);
+    const R f2 = R(fx * fx + fy * fy + z * z);
+    if (f2 > R(0)) {
+      const V d = dk[((size_t)x * N + y) * NH + z];
+      const R m = scale / f2;
+      out = V{d.x * m, d.y * m};
+    }
+  }
+  g0[i] = out;
+}
+
+// ---------------------------------------------------------------------------------------------
+// x pass.  MODE 0 (Hessian): input g0 (aligned half slot from k_prep), 3 outputs, multiplier
+// W(x)W(y)W(z) (wtab may be null: no smoothing).  MODE 1 (gradient): input the user half
+// spectrum, 2 outputs, multiplier i * scale / f^2.  Outputs: half slots.
 template <typename R, int N, int MODE>
-__global__ void __launch_bounds__((XPass<R, N, MODE>::T))
+__global__ void __launch_bounds__((Strided<R, N, +1>::T))
 k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
         const R* __restrict__ wtab, const typename Cplx<R>::type* __restrict__ tw, R scale) {
-  using X = XPass<R, N, MODE>;
-  using V = typename X::V;
-  using E = typename X::E;
-  constexpr int PS = X::PS, HZ = X::HZ, NH = N / 2 + 1;
-  constexpr size_t SLOT = (size_t)N * N * HZ;
+  using S = Strided<R, N, +1>;
+  using V = typename S::V;
+  using E = typename S::E;
+  constexpr int PS = S::PS, HZ = S::HZ, NH = N / 2 + 1, NA = MODE == 0 ? 3 : 2, M = N / E::R0;
   __shared__ V lds[E::LDS_ELEMS];
-  const int zt = blockIdx.x % X::NZT;
-  const int y = blockIdx.x / X::NZT;
+  __shared__ V s_tw[N];
   const int t = threadIdx.x;
+  load_twiddles<N, S::T>(s_tw, tw, t);
+  const int bt = xcd_tile(blockIdx.x, S::GRID);
+  const int zt = bt % S::NZT;
+  const int y = bt / S::NZT;
   const int fy = ifreq(y, N);
   V v[E::K0][E::R0];
   int zz[E::K0], jj[E::K0];
@@ -101,65 +165,66 @@ k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
     ok[k] = ok[k] && z < HZ;
     zz[k] = z;
     jj[k] = j;
+    const R wyz = (MODE == 0 && wtab != nullptr && ok[k]) ? wtab[y] * wtab[z] : R(1);
 #pragma unroll
     for (int s = 0; s < E::R0; ++s) {
-      const int n = j + s * (N / E::R0);
+      const int n = j + s * M;
       V val = V{R(0), R(0)};
-      if (ok[k] && n != N / 2 && y != N / 2) {
+      if constexpr (MODE == 0) {
+        if (ok[k]) {
+          val = in[((size_t)n * N + y) * HZ + z];
+          if (wtab != nullptr) val = cscale(val, wtab[n] * wyz);
+        }
+      } else if (ok[k] && n != N / 2 && y != N / 2) {
         const int fx = ifreq(n, N);
         const R f2 = R(fx * fx + fy * fy + z * z);
         if (f2 > R(0)) {
-          R m = scale / f2;
-          if (MODE == 0 && wtab != nullptr) m *= wtab[n] * wtab[y] * wtab[z];
+          const R m = scale / f2;
           const V d = in[((size_t)n * N + y) * NH + z];
-          val = MODE == 0 ? V{d.x * m, d.y * m} : V{-d.y * m, d.x * m};
+          val = V{-d.y * m, d.x * m};
         }
       }
       v[k][s] = val;
     }
   }
 #pragma unroll 1
-  for (int a = 0; a < X::NA; ++a) {
+  for (int a = 0; a < NA; ++a) {
     V u[E::K0][E::R0];
 #pragma unroll
     for (int k = 0; k < E::K0; ++k)
 #pragma unroll
-      for (int s = 0; s < E::R0; ++s) {
-        const int n = jj[k] + s * (N / E::R0);
-        const R fx = R(ifreq(n, N));
-        u[k][s] = cscale(v[k][s], powf_int(fx, a));
-      }
-    E::run(u, lds, tw, t);
+      for (int s = 0; s < E::R0; ++s) u[k][s] = cscale(v[k][s], powf_int(R(ifreq(jj[k] + s * M, N)), a));
+    E::run(u, lds, s_tw, t);
 #pragma unroll
     for (int k = 0; k < E::K0; ++k)
       if (ok[k]) {
 #pragma unroll
-        for (int s = 0; s < E::R0; ++s) {
-          const int n = jj[k] + s * (N / E::R0);
-          out[a * SLOT + ((size_t)n * N + y) * HZ + zz[k]] = u[k][s];
-        }
+        for (int s = 0; s < E::R0; ++s)
+          out[a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] = u[k][s];
       }
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Fused forward-x / inverse-x pass of the 2LPT displacement: reads the (z-forward, y-forward)
-// transformed source, completes the forward transform along x, multiplies by
-// i * scale * M / f^2 and runs the two inverse x transforms of fx^a (a = 0, 1).
+// transformed source from a half slot, completes the forward transform along x, multiplies by
+// i * scale * M / f^2 and runs the two inverse x transforms of fx^a (a = 0, 1) into half slots.
 template <typename R, int N>
-__global__ void __launch_bounds__((XPass<R, N, 1>::T))
+__global__ void __launch_bounds__((Strided<R, N, +1>::T))
 k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
                const typename Cplx<R>::type* __restrict__ tw, R scale) {
-  using X = XPass<R, N, 1>;
-  using V = typename X::V;
-  using E = typename X::E;
-  using EF = Engine<V, N, X::PS, 1, true, X::T, -1>;
-  constexpr int PS = X::PS, HZ = X::HZ;
-  constexpr size_t SLOT = (size_t)N * N * HZ;
+  using S = Strided<R, N, +1>;
+  using V = typename S::V;
+  using E = typename S::E;
+  using EF = Engine<V, N, S::PS, 1, true, S::T, -1>;
+  constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
   __shared__ V lds[E::LDS_ELEMS];
-  const int zt = blockIdx.x % X::NZT;
-  const int y = blockIdx.x / X::NZT;
+  __shared__ V s_tw[N];
   const int t = threadIdx.x;
+  load_twiddles<N, S::T>(s_tw, tw, t);
+  const int bt = xcd_tile(blockIdx.x, S::GRID);
+  const int zt = bt % S::NZT;
+  const int y = bt / S::NZT;
   const int fy = ifreq(y, N);
   V v[E::K0][E::R0];
   int zz[E::K0], jj[E::K0];
@@ -173,17 +238,15 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
     zz[k] = z;
     jj[k] = j;
 #pragma unroll
-    for (int s = 0; s < E::R0; ++s) {
-      const int n = j + s * (N / E::R0);
-      v[k][s] = ok[k] ? in[((size_t)n * N + y) * HZ + z] : V{R(0), R(0)};
-    }
+    for (int s = 0; s < E::R0; ++s)
+      v[k][s] = ok[k] ? in[((size_t)(j + s * M) * N + y) * HZ + z] : V{R(0), R(0)};
   }
-  EF::run(v, lds, tw, t);
+  EF::run(v, lds, s_tw, t);
 #pragma unroll
   for (int k = 0; k < E::K0; ++k)
 #pragma unroll
     for (int s = 0; s < E::R0; ++s) {
-      const int n = jj[k] + s * (N / E::R0);
+      const int n = jj[k] + s * M;
       const int fx = ifreq(n, N);
       const R f2 = R(fx * fx + fy * fy + zz[k] * zz[k]);
       const bool keep = ok[k] && n != N / 2 && y != N / 2 && f2 > R(0);
@@ -197,75 +260,58 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
 #pragma unroll
     for (int k = 0; k < E::K0; ++k)
 #pragma unroll
-      for (int s = 0; s < E::R0; ++s) {
-        const int n = jj[k] + s * (N / E::R0);
-        u[k][s] = cscale(v[k][s], powf_int(R(ifreq(n, N)), a));
-      }
-    E::run(u, lds, tw, t);
+      for (int s = 0; s < E::R0; ++s) u[k][s] = cscale(v[k][s], powf_int(R(ifreq(jj[k] + s * M, N)), a));
+    E::run(u, lds, s_tw, t);
 #pragma unroll
     for (int k = 0; k < E::K0; ++k)
       if (ok[k]) {
 #pragma unroll
-        for (int s = 0; s < E::R0; ++s) {
-          const int n = jj[k] + s * (N / E::R0);
-          out[a * SLOT + ((size_t)n * N + y) * HZ + zz[k]] = u[k][s];
-        }
+        for (int s = 0; s < E::R0; ++s)
+          out[a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] = u[k][s];
       }
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// y pass.  RECIPE 0 (Hessian): inputs a = 0, 1, 2 -> outputs b < 3 - a, slot base(a) = 0, 3, 5.
-// RECIPE 1 (gradient): inputs a = 0, 1 -> b < 2 - a, base 0, 2.  RECIPE 2 (forward, 2LPT):
-// one input, one output, DIR = -1, no multiplier.
+// y pass, packed output.  Packed component c of the recipe is (a, b, cz): input half slot a,
+// fy^b before the transform, fz^cz after it; components (2q, 2q+1) go to packed slot q as
+// C = A + iB.  The Hessian pairs are ordered so that each pair reads as few inputs as possible
+// (pair 0 reads X_1 only, pair 1 X_0 only), which lets X_2 be fetched while pair 1 runs:
+//   Hessian (RECIPE 0), packed order xy xz | yy yz | xx zz:
+//       (1,1,0) (1,0,1) | (0,2,0) (0,1,1) | (2,0,0) (0,0,2)
+//   gradient (RECIPE 1), packed order x y | z:  (1,0,0) (0,1,0) | (0,0,1)
+// hessian_component / gradient_component map the packed order back to (xx, xy, xz, yy, yz, zz)
+// and (x, y, z).
 template <int RECIPE> struct YRecipe;
 template <> struct YRecipe<0> {
-  static constexpr int NIN = 3, DIR = +1;
-  __device__ static int nout(int a) { return 3 - a; }
-  __device__ static int base(int a) { return a == 0 ? 0 : (a == 1 ? 3 : 5); }
+  static constexpr int NIN = 3, NC = 6, Q = 3;
+  static constexpr int A[6] = {1, 1, 0, 0, 2, 0}, B[6] = {1, 0, 2, 1, 0, 0}, C[6] = {0, 1, 0, 1, 0, 2};
 };
 template <> struct YRecipe<1> {
-  static constexpr int NIN = 2, DIR = +1;
-  __device__ static int nout(int a) { return 2 - a; }
-  __device__ static int base(int a) { return a == 0 ? 0 : 2; }
-};
-template <> struct YRecipe<2> {
-  static constexpr int NIN = 1, DIR = -1;
-  __device__ static int nout(int) { return 1; }
-  __device__ static int base(int) { return 0; }
+  static constexpr int NIN = 2, NC = 3, Q = 2;
+  static constexpr int A[3] = {1, 0, 0}, B[3] = {0, 1, 0}, C[3] = {0, 0, 1};
 };
 
 template <typename R, int N, int RECIPE>
-struct YPass {
-  using V = typename Cplx<R>::type;
-  static constexpr int PS = Tile<R>::PS;
-  static constexpr int HZ = N / 2;
-  static constexpr int NZT = (HZ + PS - 1) / PS;
-  using E0 = Engine<V, N, PS, 1, true, 64, YRecipe<RECIPE>::DIR>;
-  static constexpr int T = strided_threads(E0::nb(E0::R0));
-  using E = Engine<V, N, PS, 1, true, T, YRecipe<RECIPE>::DIR>;
-  static constexpr int GRID = N * NZT * YRecipe<RECIPE>::NIN;
-};
-
-template <typename R, int N, int RECIPE>
-__global__ void __launch_bounds__((YPass<R, N, RECIPE>::T))
-k_ypass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
-        const typename Cplx<R>::type* __restrict__ tw) {
-  using Y = YPass<R, N, RECIPE>;
+__global__ void __launch_bounds__((Strided<R, N, +1>::T))
+k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
+               const typename Cplx<R>::type* __restrict__ tw) {
+  using S = Strided<R, N, +1>;
   using RC = YRecipe<RECIPE>;
-  using V = typename Y::V;
-  using E = typename Y::E;
-  constexpr int PS = Y::PS, HZ = Y::HZ;
-  constexpr size_t SLOT = (size_t)N * N * HZ;
+  using V = typename S::V;
+  using E = typename S::E;
+  constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
+  constexpr size_t PSLOT = (size_t)N * N * N;
   __shared__ V lds[E::LDS_ELEMS];
-  const int zt = blockIdx.x % Y::NZT;
-  const int x = (blockIdx.x / Y::NZT) % N;
-  const int a = blockIdx.x / (Y::NZT * N);
+  __shared__ V s_tw[N];
   const int t = threadIdx.x;
-  V v[E::K0][E::R0];
+  load_twiddles<N, S::T>(s_tw, tw, t);
+  const int bt = xcd_tile(blockIdx.x, S::GRID);
+  const int zt = bt % S::NZT;
+  const int x = bt / S::NZT;
+  V v[RC::NIN][E::K0][E::R0];
   int zz[E::K0], jj[E::K0];
   bool ok[E::K0];
-  const V* src = in + a * SLOT;
 #pragma unroll
   for (int k = 0; k < E::K0; ++k) {
     int q, p, j;
@@ -275,89 +321,147 @@ k_ypass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
     zz[k] = z;
     jj[k] = j;
 #pragma unroll
-    for (int s = 0; s < E::R0; ++s) {
-      const int n = j + s * (N / E::R0);
-      v[k][s] = ok[k] ? src[((size_t)x * N + n) * HZ + z] : V{R(0), R(0)};
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int s = 0; s < E::R0; ++s)
+        v[a][k][s] = ok[k] ? in[a * S::HSLOT + ((size_t)x * N + j + s * M) * HZ + z] : V{R(0), R(0)};
   }
-  const int nout = RC::nout(a);
-  const int base = RC::base(a);
-#pragma unroll 1
-  for (int b = 0; b < nout; ++b) {
-    V u[E::K0][E::R0];
 #pragma unroll
-    for (int k = 0; k < E::K0; ++k)
+  for (int q = 0; q < RC::Q; ++q) {
+    if (RC::NIN > 2 && q == 1) {
+      // fetch X_2 for the last pair while this one runs
 #pragma unroll
-      for (int s = 0; s < E::R0; ++s) {
-        const int n = jj[k] + s * (N / E::R0);
-        u[k][s] = cscale(v[k][s], powf_int(R(ifreq(n, N)), b));
-      }
-    E::run(u, lds, tw, t);
-    V* dst = out + (size_t)(base + b) * SLOT;
+      for (int k = 0; k < E::K0; ++k)
 #pragma unroll
-    for (int k = 0; k < E::K0; ++k)
-      if (ok[k]) {
+        for (int s = 0; s < E::R0; ++s)
+          v[RC::NIN - 1][k][s] =
+              ok[k] ? in[(RC::NIN - 1) * S::HSLOT + ((size_t)x * N + jj[k] + s * M) * HZ + zz[k]] : V{R(0), R(0)};
+    }
+    // u = fy^bA fz^cA X_aA + sgn i fy^bB fz^cB X_aB; one transform per sign.  By linearity,
+    // sgn = +1 gives C[kz] = A + iB and sgn = -1 gives conj(C[N - kz]) = A - iB.
+    const int ca = 2 * q, cb = 2 * q + 1;
+    const bool has_b = cb < RC::NC;
+    V* dst = out + (size_t)q * PSLOT;
+#pragma unroll
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+      V u[E::K0][E::R0];
+#pragma unroll
+      for (int k = 0; k < E::K0; ++k)
 #pragma unroll
         for (int s = 0; s < E::R0; ++s) {
-          const int n = jj[k] + s * (N / E::R0);
-          dst[((size_t)x * N + n) * HZ + zz[k]] = u[k][s];
+          const R fy = R(ifreq(jj[k] + s * M, N)), fz = R(zz[k]);
+          const int aa = RC::A[ca];
+          const V xa = aa == 0 ? v[0][k][s] : (aa == 1 ? v[RC::NIN > 1 ? 1 : 0][k][s] : v[RC::NIN > 2 ? 2 : 0][k][s]);
+          const V ta = cscale(xa, powf_int(fy, RC::B[ca]) * powf_int(fz, RC::C[ca]));
+          if (has_b) {
+            const int ab = RC::A[has_b ? cb : ca];
+            const V xb = ab == 0 ? v[0][k][s] : (ab == 1 ? v[RC::NIN > 1 ? 1 : 0][k][s] : v[RC::NIN > 2 ? 2 : 0][k][s]);
+            const V tb = cscale(xb, powf_int(fy, RC::B[has_b ? cb : ca]) * powf_int(fz, RC::C[has_b ? cb : ca]));
+            u[k][s] = sgn > 0 ? V{ta.x - tb.y, ta.y + tb.x} : V{ta.x + tb.y, ta.y - tb.x};
+          } else {
+            u[k][s] = ta;
+          }
         }
-      }
+      if (!has_b && sgn < 0) break;   // B = 0: C[N - kz] = conj(C[kz]), written below
+      E::run(u, lds, s_tw, t);
+#pragma unroll
+      for (int k = 0; k < E::K0; ++k)
+        if (ok[k]) {
+#pragma unroll
+          for (int s = 0; s < E::R0; ++s) {
+            const size_t row = ((size_t)x * N + jj[k] + s * M) * N;
+            if (sgn > 0) {
+              dst[row + zz[k]] = u[k][s];
+              if (!has_b && zz[k] > 0) dst[row + HZ + zz[k]] = conj(u[k][s]);
+            } else if (zz[k] > 0) {
+              dst[row + HZ + zz[k]] = conj(u[k][s]);
+            }
+          }
+        }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// z pass: complex-to-real along z of NC components, packed two per complex transform
-// (c = A + iB over the full length-N spectrum, A(N-m) = conj A(m)).  Component recipes give
-// (slot, kz power): Hessian (xx, xy, xz, yy, yz, zz) = (5,0) (4,0) (3,1) (2,0) (1,1) (0,2);
-// gradient (x, y, z) = (2,0) (1,0) (0,1).
-template <int NC> struct ZRecipe;
-template <> struct ZRecipe<6> {
-  static constexpr int Q = 3;
-  __device__ static int slot(int c) { return c == 0 ? 5 : c == 1 ? 4 : c == 2 ? 3 : c == 3 ? 2 : c == 4 ? 1 : 0; }
-  __device__ static int kpow(int c) { return c == 2 || c == 4 ? 1 : (c == 5 ? 2 : 0); }
-};
-template <> struct ZRecipe<3> {
-  static constexpr int Q = 2;
-  __device__ static int slot(int c) { return c == 0 ? 2 : (c == 1 ? 1 : 0); }
-  __device__ static int kpow(int c) { return c == 2 ? 1 : 0; }
-};
+// Forward y pass of the 2LPT source: half slot -> half slot, no multiplier.
+template <typename R, int N>
+__global__ void __launch_bounds__((Strided<R, N, -1>::T))
+k_ypass_fwd(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
+            const typename Cplx<R>::type* __restrict__ tw) {
+  using S = Strided<R, N, -1>;
+  using V = typename S::V;
+  using E = typename S::E;
+  constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
+  __shared__ V lds[E::LDS_ELEMS];
+  __shared__ V s_tw[N];
+  const int t = threadIdx.x;
+  load_twiddles<N, S::T>(s_tw, tw, t);
+  const int bt = xcd_tile(blockIdx.x, S::GRID);
+  const int zt = bt % S::NZT;
+  const int x = bt / S::NZT;
+  V v[E::K0][E::R0];
+  int zz[E::K0], jj[E::K0];
+  bool ok[E::K0];
+#pragma unroll
+  for (int k = 0; k < E::K0; ++k) {
+    int q, p, j;
+    E::first_layout(t, k, q, p, j, ok[k]);
+    const int z = zt * PS + p;
+    ok[k] = ok[k] && z < HZ;
+    zz[k] = z;
+    jj[k] = j;
+#pragma unroll
+    for (int s = 0; s < E::R0; ++s)
+      v[k][s] = ok[k] ? in[((size_t)x * N + j + s * M) * HZ + z] : V{R(0), R(0)};
+  }
+  E::run(v, lds, s_tw, t);
+#pragma unroll
+  for (int k = 0; k < E::K0; ++k)
+    if (ok[k]) {
+#pragma unroll
+      for (int s = 0; s < E::R0; ++s) out[((size_t)x * N + jj[k] + s * M) * HZ + zz[k]] = v[k][s];
+    }
+}
 
+// ---------------------------------------------------------------------------------------------
+// z pass: inverse transform along z of Q packed slots (two real components each) and the
+// per-point epilogue.
 enum ZEpi { EPI_COLLAPSE = 0, EPI_STORE = 1, EPI_MU2 = 2 };
 
-template <typename R, int N, int NC, int EPI>
+template <typename R, int N, int Q, int EPI>
 struct ZPass {
   using V = typename Cplx<R>::type;
-  static constexpr int Q = ZRecipe<NC>::Q;
   using ZT = ZTile<R, N, Q>;
   static constexpr int P = ZT::P;
   static constexpr int T = ZT::T;
   static constexpr int HZ = N / 2;
-  using E = Engine<V, N, P, Q, false, T, +1>;
+  using E = Engine<V, N, P, ZT::QL, false, T, +1>;
   static constexpr int LINES = N * N;
   static constexpr int GRID = (LINES + P - 1) / P;
-  static_assert(E::K0 == Q, "z pass: one butterfly per transform per thread");
+  static_assert(E::K0 == ZT::QL, "z pass: one butterfly per transform per thread");
 };
 
 struct ZArgs {
   void* F;          // EPI_COLLAPSE: running F_max (R)
   uint8_t* ridx;    // EPI_COLLAPSE: running radius index
   int r;            // EPI_COLLAPSE: radius index of this launch
-  void* out;        // EPI_STORE: [NC][N^3] real; EPI_MU2: one workspace slot (complex)
+  int nc;           // EPI_STORE: number of real components to store (<= 2Q)
+  void* out;        // EPI_STORE: [nc][N^3] real; EPI_MU2: one half slot (complex)
   CollapseConst cc;
 };
 
-template <typename R, int N, int NC, int EPI>
-__global__ void __launch_bounds__((ZPass<R, N, NC, EPI>::T))
+template <typename R, int N, int Q, int EPI>
+__global__ void __launch_bounds__((ZPass<R, N, Q, EPI>::T))
 k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::type* __restrict__ tw, ZArgs args) {
-  using Z = ZPass<R, N, NC, EPI>;
-  using RC = ZRecipe<NC>;
+  using Z = ZPass<R, N, Q, EPI>;
   using V = typename Z::V;
   using E = typename Z::E;
-  constexpr int P = Z::P, HZ = Z::HZ, Q = Z::Q, R0 = E::R0, M0 = N / R0;
-  constexpr size_t SLOT = (size_t)N * N * HZ;
+  constexpr int P = Z::P, HZ = Z::HZ, R0 = E::R0, M0 = N / R0;
+  constexpr size_t PSLOT = (size_t)N * N * N;
   __shared__ V lds[E::LDS_ELEMS];
+  __shared__ V s_tw[N];
   const int t = threadIdx.x;
+  load_twiddles<N, Z::T>(s_tw, tw, t);
   // thread t owns pencil position (p, j) of every transform q
   const int j = t % M0;
   const int p = t / M0;
@@ -366,41 +470,51 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
   V v[Q][R0];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int ca = 2 * q, cb = 2 * q + 1;
-    const bool has_b = cb < NC;
-    const V* pa = in + (size_t)RC::slot(ca) * SLOT + (size_t)line * HZ;
-    const V* pb = in + (size_t)RC::slot(has_b ? cb : ca) * SLOT + (size_t)line * HZ;
-    const int ea = RC::kpow(ca), eb = RC::kpow(has_b ? cb : ca);
+    const V* src = in + (size_t)q * PSLOT + (size_t)line * N;
 #pragma unroll
     for (int s = 0; s < R0; ++s) {
       const int n = j + s * M0;
-      V c = V{R(0), R(0)};
-      if (line_ok && n != N / 2) {
-        const int m = n < N / 2 ? n : N - n;
-        V A = pa[m];
-        A = cscale(A, powf_int(R(m), ea));
-        V B = has_b ? cscale(pb[m], powf_int(R(m), eb)) : V{R(0), R(0)};
-        if (n > N / 2) {
-          A = conj(A);
-          B = conj(B);
-        }
-        c = V{A.x - B.y, A.y + B.x};
-      }
-      v[q][s] = c;
+      const int idx = n < HZ ? n : 3 * HZ - n;   // packed storage of C[n]
+      v[q][s] = (line_ok && n != HZ) ? src[idx] : V{R(0), R(0)};
     }
   }
-  E::run(v, lds, tw, t);
-  // v[q][s] = T_{2q}(n) + i T_{2q+1}(n) at n = j + s*M0 of line `line`
+  if constexpr (Z::ZT::QL == Q) {
+    E::run(v, lds, s_tw, t);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      V w[1][R0];
+#pragma unroll
+      for (int s = 0; s < R0; ++s) w[0][s] = v[q][s];
+      E::run(w, lds, s_tw, t);
+#pragma unroll
+      for (int s = 0; s < R0; ++s) v[q][s] = w[0][s];
+    }
+  }
+  // v[q][s] = (packed component 2q) + i (packed component 2q+1) at n = j + s*M0 of line `line`;
+  // comp(c, s) is the canonical component c (Hessian xx xy xz yy yz zz; gradient x y z).
+  auto comp = [&](int c, int s) -> R {
+    if constexpr (Q == 3) {
+      return c == 0 ? v[2][s].x : c == 1 ? v[0][s].x : c == 2 ? v[0][s].y : c == 3 ? v[1][s].x
+                                                                 : c == 4 ? v[1][s].y : v[2][s].y;
+    } else {
+      return c == 0 ? v[0][s].x : c == 1 ? v[0][s].y : v[1][s].x;
+    }
+  };
   if constexpr (EPI == EPI_COLLAPSE) {
+    static_assert(Q == 3, "collapse needs the six components");
     R* F = static_cast<R*>(args.F);
     if (line_ok) {
 #pragma unroll
       for (int s = 0; s < R0; ++s) {
-        const int n = j + s * M0;
-        const size_t idx = (size_t)line * N + n;
-        const double f = collapse_point((double)v[0][s].x, (double)v[0][s].y, (double)v[1][s].x,
-                                        (double)v[1][s].y, (double)v[2][s].x, (double)v[2][s].y, args.cc);
-        const R fr = (R)f;
+        const size_t idx = (size_t)line * N + j + s * M0;
+        R fr;
+        if constexpr (sizeof(R) == 4) {
+          fr = collapse_point_mixed(comp(0, s), comp(1, s), comp(2, s), comp(3, s), comp(4, s), comp(5, s),
+                                    (float)args.cc.sphere_gain);
+        } else {
+          fr = (R)collapse_point(comp(0, s), comp(1, s), comp(2, s), comp(3, s), comp(4, s), comp(5, s), args.cc);
+        }
         if (fr > F[idx]) {
           F[idx] = fr;
           args.ridx[idx] = (uint8_t)args.r;
@@ -415,26 +529,24 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
       for (int s = 0; s < R0; ++s) {
         const size_t idx = (size_t)line * N + j + s * M0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          out[(size_t)(2 * q) * VOL + idx] = v[q][s].x;
-          if (2 * q + 1 < NC) out[(size_t)(2 * q + 1) * VOL + idx] = v[q][s].y;
-        }
+        for (int c = 0; c < 2 * Q; ++c)
+          if (c < args.nc) out[(size_t)c * VOL + idx] = comp(c, s);
       }
     }
   } else {
-    static_assert(EPI == EPI_MU2 && NC == 6, "2LPT source needs the six components");
+    static_assert(EPI == EPI_MU2 && Q == 3, "2LPT source needs the six components");
     // mu2 at each point, then a forward real-to-complex transform along z of line pairs
-    // (2u, 2u+1) packed as one complex line.
-    R* ldsr = reinterpret_cast<R*>(lds);
+    // (2u, 2u+1) packed as one complex line, written to a half slot.
+    using EF = Engine<V, N, P / 2, 1, false, Z::T, -1>;
+    static_assert(EF::LDS_ELEMS <= E::LDS_ELEMS, "forward z tile fits the LDS of the inverse one");
 #pragma unroll
     for (int s = 0; s < R0; ++s) {
       const int n = j + s * M0;
-      const R xx = v[0][s].x, xy = v[0][s].y, xz = v[1][s].x, yy = v[1][s].y, yz = v[2][s].x, zz = v[2][s].y;
+      const R xx = comp(0, s), xy = comp(1, s), xz = comp(2, s), yy = comp(3, s), yz = comp(4, s), zz = comp(5, s);
       const R mu2 = line_ok ? (xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz) : R(0);
-      ldsr[2 * ((p >> 1) * N + n) + (p & 1)] = mu2;
+      reinterpret_cast<R*>(&lds[EF::lds_index(0, p >> 1, n)])[p & 1] = mu2;
     }
     __syncthreads();
-    using EF = Engine<V, N, P / 2, 1, false, Z::T, -1>;
     static_assert(EF::K0 == 1, "forward z: one butterfly per thread");
     V w[1][R0];
     {
@@ -444,7 +556,7 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
 #pragma unroll
       for (int s = 0; s < R0; ++s) w[0][s] = ok2 ? lds[EF::lds_index(0, p2, j2 + s * M0)] : V{R(0), R(0)};
       __syncthreads();
-      EF::run(w, lds, tw, t);
+      EF::run(w, lds, s_tw, t);
       if (ok2) {
 #pragma unroll
         for (int s = 0; s < R0; ++s) lds[EF::lds_index(0, p2, j2 + s * M0)] = w[0][s];
@@ -455,14 +567,30 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
     constexpr int NOUT = (P / 2) * HZ;
     for (int o = t; o < NOUT; o += Z::T) {
       const int u = o / HZ, k = o % HZ;
-      const V zk = lds[u * N + k];
-      const V zn = lds[u * N + ((N - k) % N)];
+      const V zk = lds[EF::lds_index(0, u, k)];
+      const V zn = lds[EF::lds_index(0, u, (N - k) % N)];
       const V a = V{R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};   // (Z_k + conj Z_{N-k})/2
       const V b = V{R(0.5) * (zk.y + zn.y), R(0.5) * (zn.x - zk.x)};   // (Z_k - conj Z_{N-k})/(2i)
       const int l0 = blockIdx.x * P + 2 * u;
       if (l0 < Z::LINES) out[(size_t)l0 * HZ + k] = a;
       if (l0 + 1 < Z::LINES) out[(size_t)(l0 + 1) * HZ + k] = b;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Per-point collapse model on caller-given tensors T6 [6][count] (xx, xy, xz, yy, yz, zz): the
+// same device functions as the z pass epilogue.
+template <typename R>
+__global__ void k_collapse_points(const R* __restrict__ t6, size_t count, R* __restrict__ F, CollapseConst cc) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const R xx = t6[i], xy = t6[count + i], xz = t6[2 * count + i];
+  const R yy = t6[3 * count + i], yz = t6[4 * count + i], zz = t6[5 * count + i];
+  if constexpr (sizeof(R) == 4) {
+    F[i] = collapse_point_mixed(xx, xy, xz, yy, yz, zz, (float)cc.sphere_gain);
+  } else {
+    F[i] = collapse_point(xx, xy, xz, yy, yz, zz, cc);
   }
 }
 

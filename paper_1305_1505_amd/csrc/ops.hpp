@@ -16,15 +16,18 @@ struct LaunchShape {
 struct SizeOps {
   int n;
   bool fp64;
-  // x pass from the user half spectrum.  mode 0: Hessian (3 outputs, window table or null);
-  // mode 1: gradient (2 outputs).  out = first workspace slot of the outputs.
+  // radius-independent Hessian input g0 = M dk scale / f^2 into one aligned slot
+  void (*prep)(const void* dk, void* g0, double scale, hipStream_t s);
+  // x pass.  mode 0: Hessian from g0 (3 outputs, window table or null); mode 1: gradient from the
+  // user half spectrum (2 outputs).  out = first workspace slot of the outputs.
   void (*xpass)(int mode, const void* dk, void* out, const void* wtab, const void* tw, double scale,
                 hipStream_t s);
   // fused forward-x / inverse-x (2LPT): one input slot -> two output slots
   void (*xpass_fwdinv)(const void* in, void* out, const void* tw, double scale, hipStream_t s);
-  // y pass: recipe 0 Hessian (3 -> 6), 1 gradient (2 -> 3), 2 forward (1 -> 1)
+  // y pass: recipe 0 Hessian (3 half slots -> 3 packed slots), 1 gradient (2 half -> 2 packed),
+  // 2 forward (1 half -> 1 half)
   void (*ypass)(int recipe, const void* in, void* out, const void* tw, hipStream_t s);
-  // z pass with the collapse epilogue at radius index r
+  // z pass (packed slots in) with the collapse epilogue at radius index r
   void (*zpass_collapse)(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain,
                          hipStream_t s);
   // z pass storing nc = 6 (Hessian) or 3 (gradient) real components to out[nc][N^3]
@@ -33,6 +36,8 @@ struct SizeOps {
   void (*zpass_mu2)(const void* in, const void* tw, void* out_slot, hipStream_t s);
   void (*grf)(void* dk, uint64_t seed, double norm, double kf, double gamma, double ns, hipStream_t s);
   void (*reset)(void* F, uint8_t* ridx, hipStream_t s);
+  // per-point collapse model on [6][count] tensors
+  void (*collapse_points)(const void* t6, size_t count, void* F, double sphere_gain, hipStream_t s);
   // launch shapes, for reports
   LaunchShape shape_x, shape_y, shape_z;
 };

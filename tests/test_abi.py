@@ -1,0 +1,72 @@
+"""The C ABI library: it loads, exports every function include/pin.h declares, and its host-only
+entry points validate arguments (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pin.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pin_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for must in ("pin_plan_create", "pin_plan_destroy", "pin_generate_field", "pin_collapse_times",
+                 "pin_collapse_times_range", "pin_displacements", "pin_deformation_tensor",
+                 "pin_inverse_collapse_time"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1305_1505_amd import binding
+
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_validation():
+    from paper_1305_1505_amd import binding as B
+
+    assert B.pin_size_supported(512) and B.pin_size_supported(768) and not B.pin_size_supported(500)
+    B.pin_plan_validate(B.make_desc(64, 100.0, [20.0, 10.0, 1.0]))
+    bad = [
+        (B.make_desc(64, 100.0, [1.0, 2.0]), B.PIN_ERR_INVALID_ARG),       # increasing radii
+        (B.make_desc(64, 100.0, [1.0, 1.0]), B.PIN_ERR_INVALID_ARG),       # repeated radius
+        (B.make_desc(64, -1.0, [1.0]), B.PIN_ERR_INVALID_ARG),             # box
+        (B.make_desc(64, 100.0, [-1.0]), B.PIN_ERR_INVALID_ARG),           # radius sign
+        (B.make_desc(100, 100.0, [1.0]), B.PIN_ERR_UNSUPPORTED_SIZE),      # size
+        (B.make_desc(64, 100.0, [1.0], sigma8=0.0), B.PIN_ERR_INVALID_ARG),
+        (B.make_desc(64, 100.0, [1.0], prec=7), B.PIN_ERR_INVALID_ARG),
+        (B.make_desc(64, 100.0, [float(255 - i) for i in range(255)]), B.PIN_ERR_INVALID_ARG),
+    ]
+    for desc, status in bad:
+        with pytest.raises(B.PinError) as e:
+            B.pin_plan_validate(desc)
+        assert e.value.status == status
+        assert B.pin_last_error()
+
+
+def test_workspace_bytes_formula():
+    from paper_1305_1505_amd import binding as B
+
+    n, nr = 512, 40
+    got = B.pin_plan_workspace_bytes(B.make_desc(n, 1000.0, [float(nr - i) for i in range(nr)]))
+    slot = n * n * (n // 2) * 8
+    assert got == 11 * slot + n * 8 + n * nr * 4
+
+
+def test_status_strings():
+    from paper_1305_1505_amd import binding as B
+
+    for s in range(10):
+        assert B.pin_status_string(s) not in ("", "unknown status")
+    names = [B.pin_kernel_class_name(i) for i in range(B.pin_kernel_class_count())]
+    assert "zpass_collapse" in names and len(set(names)) == len(names)

@@ -128,8 +128,15 @@ def test_collapse_per_point_function_fp64(lib):
     f = _host(F)
     wk = np.exp(-0.5 * (2 * np.pi * m * radius / n) ** 2)
     assert abs(f[0, 0, 0] - 3 * amp * wk / collapse.DELTA_C) < 1e-12
-    ref = run.per_radius_F(spec, radius)
-    assert np.max(np.abs(f - np.maximum(ref, 0))) < 1e-11
+    t6 = hessian.deformation_tensor(spec, radius)
+    ref = np.maximum(collapse.inverse_collapse_time(t6), 0)
+    l1 = collapse.largest_eigenvalue(t6)
+    # where lambda_1 is clearly positive F is well conditioned; where the tensor is a negative
+    # plane (lambda_1 = lambda_2 = 0 up to FFT rounding) the cubic's root is the cube root of that
+    # rounding on both sides (the oracle itself moves by ~1e-6 under 1e-16 input noise)
+    good = l1 > 1e-8
+    assert np.max(np.abs(f - ref)[good]) < 1e-11
+    assert np.max(f[~good]) < 1e-5
     plan.close()
 
 
@@ -173,4 +180,20 @@ def test_displacements_fp32(lib):
     r1, r2 = run.displacements(dk_ref, box)
     assert metrics.rel_rms(_host(p1).astype(np.float64), r1) <= 1e-5
     assert metrics.rel_rms(_host(p2).astype(np.float64), r2) <= 1e-5
+    plan.close()
+
+
+def test_config_c64_fp32_end_to_end(lib):
+    """64^3, 100 Mpc/h, 16 radii, float32 FFTs: F within 1e-5 relative RMS of the FP64 oracle and
+    the collapse radius unchanged for all but 1e-4 of the points."""
+    cfg = W.CONFIGS["c64_fp64"]
+    n, box, seed = cfg["n"], cfg["box"], cfg["seed"]
+    radii = W.config_radii(cfg)
+    plan = _plan(lib, n, radii, lib.PIN_FP32, box)
+    dk_ref = field.linear_field(seed, n, box, W.SIGMA8, W.GAMMA, W.NS)
+    F, R = plan.collapse_times(_to_dev(dk_ref, plan))
+    f_ref, r_ref = run.collapse_times(dk_ref, radii)
+    f, r = _host(F).astype(np.float64), _host(R)
+    assert metrics.rel_rms(f, f_ref) <= 1e-5
+    assert metrics.mismatch_fraction(r, r_ref) <= 1e-4
     plan.close()
