@@ -62,6 +62,117 @@ def cpu_baseline(sample_n=64, radius_stride=4):
                       f"float64 NumPy/SciPy, {os.cpu_count()} host cores visible"}
 
 
+def serve_bench(B, W, full=False):
+    """Serving workload: Poisson arrivals (4/s) of mixed-size realizations against a 200 GB budget.
+
+    Phases: warm-up (creates slots and graphs), the measured list replayed at its arrival times
+    (p50/p99 latency), the same list submitted at once (served throughput), and the same list run
+    one request after another through the plain entry points on one plan per grid size.
+    """
+    import threading
+
+    import torch
+
+    trace = W.serve_trace(count=None if full else 10 + 60)
+    warm = W.SERVE["warmup"] if full else 10
+    cfg = B.make_serve_config(W.SERVE["hbm_budget"], max_slots_per_class=4)
+    srv = B.pin_serve_create(cfg)
+
+    def run(reqs, paced):
+        outstanding, lock, stop = [], threading.Lock(), threading.Event()
+        failures = []
+
+        def collector():
+            while not stop.is_set() or outstanding:
+                with lock:
+                    cur = list(outstanding)
+                for t in cur:
+                    st, _ = B.pin_serve_poll(srv, t)
+                    if st == B.PIN_ERR_NOT_READY:
+                        continue
+                    if st != B.PIN_OK:
+                        failures.append((t, st))
+                    B.pin_serve_release(srv, t)
+                    with lock:
+                        outstanding.remove(t)
+                time.sleep(0.0005)
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t0 = time.perf_counter()
+        base = reqs[0]["t"]
+        for r in reqs:
+            if paced:
+                delay = (r["t"] - base) - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            t = B.pin_serve_submit(srv, B.make_request(r["seed"], r["n"], r["box"], r["radii"], 1))
+            with lock:
+                outstanding.append(t)
+        stop.set()
+        th.join()
+        if failures:
+            raise RuntimeError(f"served requests failed: {failures[:5]}")
+        return time.perf_counter() - t0
+
+    run(trace[:warm], paced=True)
+    measured = trace[warm:]
+    updates = sum(r["n"] ** 3 * len(r["radii"]) for r in measured)
+    B.pin_serve_reset_stats(srv)
+    wall_paced = run(measured, paced=True)
+    paced = B.pin_serve_stats(srv)
+    B.pin_serve_reset_stats(srv)
+    wall_sat = run(measured, paced=False)
+    sat = B.pin_serve_stats(srv)
+    B.pin_serve_destroy(srv)
+    torch.cuda.synchronize()
+
+    # plain path: the same list, one request after another, one plan per grid size
+    plans = {}
+    stream = torch.cuda.current_stream().cuda_stream
+    maxr = W.SERVE["n_radii"][1]
+    for n in sorted({r["n"] for r in measured}):
+        pl = B.Plan(n, 2.0 * n, W.radii_cells(maxr, W.SERVE["r_max"], W.SERVE["r_min"]), prec=B.PIN_FP32)
+        bufs = (pl.empty_spectrum(), torch.empty((n, n, n), dtype=torch.float32, device="cuda"),
+                torch.empty((n, n, n), dtype=torch.uint8, device="cuda"),
+                torch.empty((3, n, n, n), dtype=torch.float32, device="cuda"),
+                torch.empty((3, n, n, n), dtype=torch.float32, device="cuda"))
+        plans[n] = (pl, bufs)
+
+    def plain_one(r):
+        pl, (dk, F, R, p1, p2) = plans[r["n"]]
+        assert r["box"] == 2.0 * r["n"]            # the trace's box; the plan was made with it
+        B.pin_plan_set_radii(pl.handle, r["radii"], stream)
+        B.pin_generate_field(pl.handle, r["seed"], dk.data_ptr(), stream)
+        B.pin_collapse_times(pl.handle, dk.data_ptr(), F.data_ptr(), R.data_ptr(), stream)
+        B.pin_displacements(pl.handle, dk.data_ptr(), p1.data_ptr(), p2.data_ptr(), stream)
+
+    for r in measured[:5]:
+        plain_one(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in measured:
+        plain_one(r)
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
+    for pl, bufs in plans.values():
+        pl.close()
+    del plans
+    torch.cuda.empty_cache()
+    served_rate = updates / wall_sat
+    plain_rate = updates / wall_plain
+    return {
+        "requests": len(measured), "warmup": warm, "rate_per_s": W.SERVE["rate_per_s"],
+        "sizes": list(W.SERVE["sizes"]), "budget_bytes": W.SERVE["hbm_budget"],
+        "p50_latency_s": round(paced["p50_s"], 4), "p99_latency_s": round(paced["p99_s"], 4),
+        "mean_latency_s": round(paced["mean_s"], 4), "paced_wall_s": round(wall_paced, 2),
+        "served_updates_per_s_saturated": served_rate, "plain_updates_per_s": plain_rate,
+        "served_over_plain": round(served_rate / plain_rate, 3),
+        "saturated_p99_latency_s": round(sat["p99_s"], 4),
+        "note": "plain = the same requests one after another through pin_* on one plan per grid size",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +181,8 @@ def main():
     ap.add_argument("--config", default="c512_fp32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-full", action="store_true", help="full serving trace (20 + 300 requests)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -175,6 +288,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    serve_out = None
+    if not args.no_serve and args.config == "c512_fp32":
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        serve_out = serve_bench(B, W, full=args.serve_full)
+        print(f"[bench] serving: p99 {serve_out['p99_latency_s']} s, served/plain "
+              f"{serve_out['served_over_plain']}", file=sys.stderr, flush=True)
+
     base = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -200,6 +320,7 @@ def main():
         "fp64": fp64,
         "roofline": roofline,
         "kernels": per_kernel,
+        "serve": serve_out,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

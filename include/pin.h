@@ -89,6 +89,12 @@ pin_status pin_plan_validate(const pin_plan_desc* desc);
  * window tables, and allocates the FFT workspace.  *out receives the handle. */
 pin_status pin_plan_create(const pin_plan_desc* desc, pin_plan* out);
 
+/* Replace the plan's radius list (section "Collapse times": the smoothing radii): n_radii must
+ * not exceed the count the plan was created with; the radii follow the rules of pin_plan_desc
+ * (copied).  The new window tables are uploaded on `stream` and the call returns once the copy
+ * is done; work queued earlier on other streams must not be using this plan. */
+pin_status pin_plan_set_radii(pin_plan plan, const double* radii_cells, int n_radii, hipStream_t stream);
+
 /* Free the plan and its device memory (waits for the device to go idle first). */
 pin_status pin_plan_destroy(pin_plan plan);
 
@@ -147,6 +153,75 @@ const char* pin_kernel_class_name(int cls);
 pin_status pin_plan_set_timing(pin_plan plan, int enable); /* enabling also resets the totals   */
 /* Waits for the recorded events, then returns the summed duration (ms) and launch count. */
 pin_status pin_plan_kernel_time(pin_plan plan, int cls, double* total_ms, long long* launches);
+
+/* ------------------------------------------------------------------------------------------
+ * Serving: continuous batching of realization requests (seed, grid size, box, radii) of uneven
+ * sizes as they arrive.  A server owns per-size-class "slots" (a plan workspace, the field and
+ * the outputs of one request, and a stream of its own); a request is admitted when a slot of its
+ * class is idle or a new one fits the device-memory budget (idle slots of other classes are
+ * evicted, least recently used first), and its whole path -- field, collapse times over its
+ * radii, optionally ZA and 2LPT displacements -- is then queued on that slot's stream as one
+ * captured hipGraph (cached per slot for each radius count, box and displacement choice).
+ * Admitted requests therefore run concurrently; within a size class admission is first come,
+ * first served.  Every request's result is computed by the same kernels with the same inputs
+ * whatever else is in flight, so it is bitwise identical alone and in a mix.  All server calls
+ * are thread-safe.  Results are device pointers owned by the server until pin_serve_release. */
+typedef struct pin_server_s* pin_server;
+
+typedef struct {
+  uint64_t seed;             /* field seed (pin_generate_field)                            */
+  int n;                     /* grid size (pin_size_supported)                              */
+  double box;                /* Mpc/h, > 0                                                  */
+  int n_radii;               /* 1..254                                                      */
+  const double* radii_cells; /* host, strictly decreasing, > 0; copied by pin_serve_submit  */
+  int want_disp;             /* 1: also psi1 and psi2                                       */
+} pin_request;
+
+typedef struct {
+  const void* F;             /* device [N^3] F_max (server precision)                       */
+  const uint8_t* ridx;       /* device [N^3] radius index of F_max, 255 = never             */
+  const void* psi1;          /* device [3][N^3] or NULL                                     */
+  const void* psi2;          /* device [3][N^3] or NULL                                     */
+  int n, n_radii;
+  double t_submit, t_admit, t_done;   /* seconds since the server was created              */
+  pin_status status;
+} pin_result;
+
+typedef struct {
+  double hbm_budget_bytes;   /* device bytes all slots together may hold                   */
+  int max_slots_per_class;   /* concurrent requests per grid size, >= 1                     */
+  int device;                /* HIP device ordinal                                          */
+  pin_precision prec;
+  double sigma8, gamma, ns;  /* spectrum, as in pin_plan_desc                               */
+} pin_serve_config;
+
+typedef struct {
+  double p50_s, p99_s, mean_s;   /* latency submit -> done of completed requests            */
+  double updates_per_s;          /* sum of N^3 n_radii completed / (last done - first submit) */
+  double hbm_in_use;             /* bytes held by slots                                     */
+  long long completed, failed, cancelled, queued, running, slots;
+} pin_serve_stats_t;
+
+/* Device bytes one slot of grid size n holds (host only; the admission unit). */
+pin_status pin_serve_slot_bytes(const pin_serve_config* cfg, int n, size_t* bytes);
+pin_status pin_serve_create(const pin_serve_config* cfg, pin_server* out);
+/* Validate and copy the request, return a ticket; never blocks.  PIN_ERR_BUDGET if a slot of
+ * this size can never fit the budget; PIN_ERR_SHUTDOWN after pin_serve_destroy began. */
+pin_status pin_serve_submit(pin_server srv, const pin_request* req, uint64_t* ticket);
+/* PIN_ERR_NOT_READY while queued or running; PIN_OK with *out filled when done; the request's
+ * failure status (PIN_ERR_DEVICE, PIN_ERR_CANCELLED, ...) otherwise. */
+pin_status pin_serve_poll(pin_server srv, uint64_t ticket, pin_result* out);
+/* As poll, blocking up to timeout_s seconds (PIN_ERR_TIMEOUT after that). */
+pin_status pin_serve_wait(pin_server srv, uint64_t ticket, double timeout_s, pin_result* out);
+/* Queued: removed (PIN_ERR_CANCELLED).  Running: its result is discarded when the device work
+ * ends.  Finished: no effect. */
+pin_status pin_serve_cancel(pin_server srv, uint64_t ticket);
+/* Forget a finished request and free its slot for the next one (invalidates its pointers). */
+pin_status pin_serve_release(pin_server srv, uint64_t ticket);
+pin_status pin_serve_stats(pin_server srv, pin_serve_stats_t* out);
+pin_status pin_serve_reset_stats(pin_server srv);
+/* Stop admitting, cancel queued requests, wait for running ones, free all device memory. */
+pin_status pin_serve_destroy(pin_server srv);
 
 const char* pin_status_string(pin_status status);
 const char* pin_last_error(void);

@@ -54,6 +54,7 @@ _sig = {
     "pin_plan_validate": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc)]),
     "pin_plan_create": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(_vp)]),
     "pin_plan_destroy": (ctypes.c_int, [_vp]),
+    "pin_plan_set_radii": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int, _vp]),
     "pin_generate_field": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, _vp]),
     "pin_collapse_reset": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pin_collapse_times_range": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
@@ -75,9 +76,9 @@ for _name, (_res, _args) in _sig.items():
     _f.argtypes = _args
 
 
-def _check(status):
+def _check(status, library=None):
     if status != PIN_OK:
-        raise PinError(status, lib.pin_last_error().decode())
+        raise PinError(status, (library or lib).pin_last_error().decode())
 
 
 def make_desc(n, box, radii_cells, sigma8=0.8, gamma=0.21, ns=1.0, prec=PIN_FP32):
@@ -110,6 +111,11 @@ def pin_plan_create(desc):
 
 def pin_plan_destroy(plan):
     _check(lib.pin_plan_destroy(plan))
+
+
+def pin_plan_set_radii(plan, radii_cells, stream=0):
+    radii = (ctypes.c_double * len(radii_cells))(*[float(r) for r in radii_cells])
+    _check(lib.pin_plan_set_radii(plan, radii, len(radii_cells), _vp(stream)))
 
 
 def pin_generate_field(plan, seed, dk, stream=0):
@@ -253,3 +259,133 @@ class Plan:
         pin_displacements(self.handle, dk.data_ptr(), p1.data_ptr() if p1 is not None else 0,
                           p2.data_ptr() if p2 is not None else 0, self._stream())
         return p1, p2
+
+
+# ---------------------------------------------------------------------------------------------
+# Serving (pin_serve_*)
+
+class pin_request(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n", ctypes.c_int), ("box", ctypes.c_double),
+                ("n_radii", ctypes.c_int), ("radii_cells", ctypes.POINTER(ctypes.c_double)),
+                ("want_disp", ctypes.c_int)]
+
+
+class pin_result(ctypes.Structure):
+    _fields_ = [("F", _vp), ("ridx", _vp), ("psi1", _vp), ("psi2", _vp), ("n", ctypes.c_int),
+                ("n_radii", ctypes.c_int), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class pin_serve_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("max_slots_per_class", ctypes.c_int),
+                ("device", ctypes.c_int), ("prec", ctypes.c_int), ("sigma8", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("ns", ctypes.c_double)]
+
+
+class pin_serve_stats_t(ctypes.Structure):
+    _fields_ = [("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("updates_per_s", ctypes.c_double), ("hbm_in_use", ctypes.c_double),
+                ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("cancelled", ctypes.c_longlong), ("queued", ctypes.c_longlong),
+                ("running", ctypes.c_longlong), ("slots", ctypes.c_longlong)]
+
+
+_serve_sig = {
+    "pin_serve_slot_bytes": (ctypes.c_int, [ctypes.POINTER(pin_serve_config), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+    "pin_serve_create": (ctypes.c_int, [ctypes.POINTER(pin_serve_config), ctypes.POINTER(_vp)]),
+    "pin_serve_submit": (ctypes.c_int, [_vp, ctypes.POINTER(pin_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "pin_serve_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(pin_result)]),
+    "pin_serve_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(pin_result)]),
+    "pin_serve_cancel": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "pin_serve_release": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "pin_serve_stats": (ctypes.c_int, [_vp, ctypes.POINTER(pin_serve_stats_t)]),
+    "pin_serve_reset_stats": (ctypes.c_int, [_vp]),
+    "pin_serve_destroy": (ctypes.c_int, [_vp]),
+}
+
+
+class ServeAPI:
+    """The pin_serve_* calls of one library (libpin.so, or a test double with the same ABI)."""
+
+    def __init__(self, library):
+        self.lib = library
+        for name, (res, args) in _serve_sig.items():
+            f = getattr(library, name)
+            f.restype = res
+            f.argtypes = args
+        library.pin_last_error.restype = ctypes.c_char_p
+        library.pin_last_error.argtypes = []
+
+    def check(self, status):
+        _check(status, self.lib)
+
+    def pin_serve_slot_bytes(self, cfg, n):
+        out = ctypes.c_size_t(0)
+        self.check(self.lib.pin_serve_slot_bytes(ctypes.byref(cfg), int(n), ctypes.byref(out)))
+        return out.value
+
+    def pin_serve_create(self, cfg):
+        h = _vp()
+        self.check(self.lib.pin_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        return h
+
+    def pin_serve_submit(self, srv, req):
+        t = ctypes.c_uint64(0)
+        self.check(self.lib.pin_serve_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def pin_serve_poll(self, srv, ticket):
+        """(status, pin_result) without raising on NOT_READY or a failed request."""
+        out = pin_result()
+        st = self.lib.pin_serve_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(out))
+        return st, out
+
+    def pin_serve_wait(self, srv, ticket, timeout_s):
+        out = pin_result()
+        st = self.lib.pin_serve_wait(srv, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(out))
+        return st, out
+
+    def pin_serve_cancel(self, srv, ticket):
+        self.check(self.lib.pin_serve_cancel(srv, ctypes.c_uint64(ticket)))
+
+    def pin_serve_release(self, srv, ticket):
+        self.check(self.lib.pin_serve_release(srv, ctypes.c_uint64(ticket)))
+
+    def pin_serve_stats(self, srv):
+        out = pin_serve_stats_t()
+        self.check(self.lib.pin_serve_stats(srv, ctypes.byref(out)))
+        return {k: getattr(out, k) for k, _ in pin_serve_stats_t._fields_}
+
+    def pin_serve_reset_stats(self, srv):
+        self.check(self.lib.pin_serve_reset_stats(srv))
+
+    def pin_serve_destroy(self, srv):
+        self.check(self.lib.pin_serve_destroy(srv))
+
+
+def make_request(seed, n, box, radii_cells, want_disp=1):
+    radii = (ctypes.c_double * len(radii_cells))(*[float(r) for r in radii_cells])
+    r = pin_request(ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), int(n), float(box), len(radii_cells), radii,
+                    int(want_disp))
+    r._radii = radii
+    return r
+
+
+def make_serve_config(budget_bytes, max_slots_per_class=4, device=0, prec=PIN_FP32, sigma8=0.8, gamma=0.21,
+                      ns=1.0):
+    return pin_serve_config(float(budget_bytes), int(max_slots_per_class), int(device), int(prec), float(sigma8),
+                            float(gamma), float(ns))
+
+
+serve = ServeAPI(lib)
+pin_serve_slot_bytes = serve.pin_serve_slot_bytes
+pin_serve_create = serve.pin_serve_create
+pin_serve_submit = serve.pin_serve_submit
+pin_serve_poll = serve.pin_serve_poll
+pin_serve_wait = serve.pin_serve_wait
+pin_serve_cancel = serve.pin_serve_cancel
+pin_serve_release = serve.pin_serve_release
+pin_serve_stats = serve.pin_serve_stats
+pin_serve_reset_stats = serve.pin_serve_reset_stats
+pin_serve_destroy = serve.pin_serve_destroy

@@ -23,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-HOST_SOURCES = ["capi.cpp", "host_math.cpp", "registry.cpp"]
+HOST_SOURCES = ["capi.cpp", "plan.cpp", "serve.cpp", "host_math.cpp", "registry.cpp"]
 
 
 def sizes():
