@@ -37,6 +37,24 @@ def algorithmic_bytes(cls, n, real_bytes):
     }.get(cls)
 
 
+def measured_traffic(cls, n, prec):
+    """HBM bytes per launch (fetch + write) of kernel `cls` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources at this workload; else None."""
+    from paper_1305_1505_amd import binding as B
+    from paper_1305_1505_amd import profile_summary
+
+    path = os.path.join(ROOT, "profiles", "traffic_c512_fp32.json")
+    if n != 512 or prec != B.PIN_FP32 or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256") != profile_summary.kernel_source_hash() or cls not in t["kernels"]:
+        return None
+    k = t["kernels"][cls]
+    return {"bytes": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
+            "write_bytes": k["write_bytes"], "source": "profiles/traffic_c512_fp32.json"}
+
+
 def cpu_baseline(sample_n=64, radius_stride=4):
     """The FP64 oracle on a bounded sample of the workload: a sample_n^3 grid with the same cell
     size (box scaled), every radius_stride-th radius, full step (field, collapse, displacements)."""
@@ -184,7 +202,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-full", action="store_true", help="full serving trace (20 + 300 requests)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+                    help="also run three plain 1 GiB device copies (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -243,9 +261,11 @@ def main():
     dom = max(("xpass_hessian", "ypass_hessian", "zpass_collapse"), key=lambda k: kernels[k]["total_ms"])
     dom_bytes = algorithmic_bytes(dom, n, real_bytes)
     achieved = dom_bytes / (kernels[dom]["avg_ms"] * 1e-3) / 1e9
+    measured = measured_traffic(dom, n, prec)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": dom_bytes}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(measured["bytes"]) if measured else None,
+                "traffic_detail": measured, "bytes_per_launch": dom_bytes}
     per_kernel = {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"],
                       "GB/s": (round(algorithmic_bytes(k, n, real_bytes) / (v["avg_ms"] * 1e-3) / 1e9, 1)
                                if algorithmic_bytes(k, n, real_bytes) else None)}

@@ -1,0 +1,132 @@
+"""Summaries of rocprofv3 output for this library (run on the host after a profiled run).
+
+    python -m paper_1305_1505_amd.profile_summary trace  <kernel_stats.csv> [out.md]
+    python -m paper_1305_1505_amd.profile_summary traffic <fetch counter_collection.csv>
+                                                         <write counter_collection.csv> <out.json> [out.md]
+
+`trace` turns a `rocprofv3 --kernel-trace --stats --output-format csv` kernel-stats file into a
+markdown table.  `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+`bench.py --copy-probe` into HBM bytes per dispatch for each kernel, each counter scaled by what
+it reads for the plain device copies of the probe (three 1 GiB copies,
+`__amd_rocclr_copyBuffer`, all dispatches together), and records the hash of the kernel sources the counters belong to:
+`bench.py` reports the traffic only while the sources still hash to that value.
+"""
+
+import csv
+import hashlib
+import json
+import os
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+KERNEL_SOURCES = ("kernels.hpp", "fft_core.hpp", "collapse_dev.hpp", "trig_poly.hpp", "grf.hpp", "inst.hip")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 3 << 30          # bench.py --copy-probe copies 2^28 float32 (1 GiB) three times
+
+# kernel-class name used by bench.py -> substring of the kernel name at N = 512, float32
+KERNEL_KEYS = {
+    "xpass_hessian": "k_xpass<float, 512, 0>",
+    "ypass_hessian": "k_ypass_packed<float, 512, 0>",
+    "zpass_collapse": "k_zpass<float, 512, 3, 0>",
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def _rows(path):
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def per_kernel_counter(path, counter):
+    """{kernel name: [(grid size, value) per dispatch]} for one counter (KiB as rocprofv3 reports
+    them; rows repeated for one dispatch are counted once)."""
+    out, seen = {}, set()
+    for r in _rows(path):
+        if r.get("Counter_Name") != counter or r["Dispatch_Id"] in seen:
+            continue
+        seen.add(r["Dispatch_Id"])
+        out.setdefault(r["Kernel_Name"], []).append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return out
+
+
+def _probe_kib(per_kernel):
+    """Counter total over the copy probe's dispatches: the copy-kernel launches with the largest
+    grid (other copies the runtime makes are small)."""
+    copies = [gv for k, gvs in per_kernel.items() if COPY_KERNEL in k for gv in gvs]
+    if not copies:
+        raise SystemExit("the copy probe is missing from the counter runs")
+    g = max(gv[0] for gv in copies)
+    return sum(v for grid, v in copies if grid == g)
+
+
+def traffic(fetch_csv, write_csv):
+    fetch = per_kernel_counter(fetch_csv, "FETCH_SIZE")
+    write = per_kernel_counter(write_csv, "WRITE_SIZE")
+    sf = COPY_BYTES / (_probe_kib(fetch) * 1024.0)
+    sw = COPY_BYTES / (_probe_kib(write) * 1024.0)
+    kernels = {}
+    for cls, key in KERNEL_KEYS.items():
+        fk = [v for k, gvs in fetch.items() if key in k for _, v in gvs]
+        wk = [v for k, gvs in write.items() if key in k for _, v in gvs]
+        if fk and wk:
+            kernels[cls] = {"fetch_bytes": sf * 1024.0 * sum(fk) / len(fk),
+                            "write_bytes": sw * 1024.0 * sum(wk) / len(wk),
+                            "dispatches": len(fk)}
+    return {"kernel_source_sha256": kernel_source_hash(), "copy_scale_fetch": sf, "copy_scale_write": sw,
+            "kernels": kernels}
+
+
+def traffic_table(t):
+    lines = [f"copy calibration: FETCH_SIZE x {t['copy_scale_fetch']:.4f}, WRITE_SIZE x {t['copy_scale_write']:.4f}",
+             "", "| kernel | dispatches | fetch GB / launch | write GB / launch | total GB / launch |",
+             "|---|---:|---:|---:|---:|"]
+    for cls, k in t["kernels"].items():
+        lines.append(f"| {cls} | {k['dispatches']} | {k['fetch_bytes'] / 1e9:.4f} | {k['write_bytes'] / 1e9:.4f} | "
+                     f"{(k['fetch_bytes'] + k['write_bytes']) / 1e9:.4f} |")
+    lines.append(f"\nkernel sources sha256: `{t['kernel_source_sha256']}`")
+    return "\n".join(lines)
+
+
+def trace_table(stats_csv):
+    rows = _rows(stats_csv)
+    lines = ["| kernel | calls | total ns | average ns | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:16]:
+        name = r.get("Name", "")
+        name = name if len(name) < 90 else name[:87] + "..."
+        lines.append(f"| `{name}` | {r.get('Calls')} | {r.get('TotalDurationNs')} | "
+                     f"{float(r.get('AverageNs', 0)):.0f} | {float(r.get('Percentage', 0)):.2f} |")
+    return "\n".join(lines)
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "trace":
+        table = trace_table(argv[1])
+        if len(argv) > 2:
+            with open(argv[2], "a") as fh:
+                fh.write(table + "\n")
+        print(table)
+    elif len(argv) >= 4 and argv[0] == "traffic":
+        t = traffic(argv[1], argv[2])
+        with open(argv[3], "w") as fh:
+            json.dump(t, fh, indent=1)
+            fh.write("\n")
+        table = traffic_table(t)
+        if len(argv) > 4:
+            with open(argv[4], "a") as fh:
+                fh.write(table + "\n")
+        print(table)
+    else:
+        print(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
