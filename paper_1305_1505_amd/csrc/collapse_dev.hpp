@@ -152,38 +152,38 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
 // discriminants 4p^6 - det(B)^2 (= 4p^6 (1 - r^2)) and hq^2 + p3^3 of the depressed collapse
 // cubic -- are formed in float64 (full rate on gfx950, no transcendental functions).  From them
 // 1 + r and 1 + r_c are known to float32 relative accuracy even as r -> -1, so the remaining
-// square roots, cube roots and c(r) = cos(arccos(r)/3) (polynomials of trig_poly.hpp) run in
-// float32 without the usual sqrt(eps) loss at lambda_1 ~ lambda_2 or at a double root.  lambda_1
-// and the collapse root each get one float64 Newton step (on the characteristic polynomial of T
-// and on P); the Newton step on lambda_1 is skipped where the characteristic polynomial is near
-// a multiple root (there the closed form is already accurate).
+// square roots, cube roots and c(r) = cos(arccos(r)/3) run in float32 without the usual sqrt(eps)
+// loss at lambda_1 ~ lambda_2 or at a double root: c(r) = U(sqrt(1 + r)) is one polynomial over
+// all of [-1, 1] (trig_poly.hpp), so no lane branches on the sign of r.  lambda_1 and the collapse
+// root each get one float64 Newton step (on the characteristic polynomial of B = T - m I and on
+// P); the Newton step on lambda_1 is skipped where that polynomial is near a double root (there
+// the closed form is already accurate).
 
-// c(r) = cos(arccos(r)/3); for r < 0, opr = 1 + r supplied by the caller.
-__device__ __forceinline__ float acos3_cos(float r, float opr) {
-  const bool pos = r >= 0.f;
-  const float x = pos ? r : __builtin_sqrtf(fmaxf(opr, 0.f));
-  float y = pos ? kAcos3A[8] : kAcos3B[8];
+// c(r) = cos(arccos(r)/3) from opr = 1 + r.
+__device__ __forceinline__ float acos3_cos(float opr) {
+  const float u = __builtin_amdgcn_sqrtf(fmaxf(opr, 0.f));
+  float y = kAcos3U[8];
 #pragma unroll
-  for (int k = 7; k >= 0; --k) y = fmaf(y, x, pos ? kAcos3A[k] : kAcos3B[k]);
+  for (int k = 7; k >= 0; --k) y = fmaf(y, u, kAcos3U[k]);
   return y;
 }
 
 __device__ __forceinline__ float fast_cbrt(float v) {
-  // sign(v) |v|^(1/3): hardware log2/exp2, then one Newton step y <- y - (y^3 - v)/(3 y^2)
+  // sign(v) |v|^(1/3) from the hardware log2/exp2 (a few ulp; the float64 Newton step on the
+  // collapse cubic that follows removes the error)
   const float a = fabsf(v);
-  if (a == 0.f) return 0.f;
-  float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a) * (1.f / 3.f));
-  y = y - (y * y * y - a) * __builtin_amdgcn_rcpf(3.f * y * y);
-  return copysignf(y, v);
+  const float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a) * (1.f / 3.f));
+  return a == 0.f ? 0.f : copysignf(y, v);
 }
 
-// 1 + r from r and the float64 pair (num, den) with 1 - r^2 = num/den (num, den same sign);
-// falls back to 1 + r if den is not representable in float32.
+// 1 + r for r in [-1, 1], given the float64 pair (num, den) with 1 - r^2 = num/den (num, den of
+// one sign).  For r < 0 it is (1 - r^2)/(1 - r), free of the cancellation in 1 + r; for r >= 0,
+// or if den is not representable in float32, plain 1 + r.
 __device__ __forceinline__ float one_plus_r(float r, double num, double den) {
   const float dn = (float)den;
-  if (!(fabsf(dn) > 0.f) || !(fabsf(dn) < 3.0e38f)) return 1.f + r;
-  const float omr2 = fmaxf(0.f, (float)num * __builtin_amdgcn_rcpf(dn));
-  return omr2 * __builtin_amdgcn_rcpf(1.f - fminf(r, 0.f));
+  const float viaq = fmaxf(0.f, (float)num * __builtin_amdgcn_rcpf(dn * (1.f - r)));
+  const bool usable = r < 0.f && fabsf(dn) > 0.f && fabsf(dn) < 1.0e38f;
+  return usable ? viaq : 1.f + r;
 }
 
 __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, float fxz, float fyy, float fyz,
@@ -195,21 +195,24 @@ __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, floa
   const double off = xy * xy + xz * xz + yz * yz;
   const double p2 = (bxx * bxx + byy * byy + bzz * bzz + 2.0 * off) * (1.0 / 6.0);
   const double detb = bxx * (byy * bzz - yz * yz) - xy * (xy * bzz - yz * xz) + xz * (xy * yz - byy * xz);
-  const double mu2 = xx * yy + xx * zz + yy * zz - off;
-  const double mu3 = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
-  const float p = __builtin_sqrtf((float)p2);
-  float r = 0.f, opr = 1.f;
-  if (p2 > 0.0) {
-    r = fminf(1.f, fmaxf(-1.f, (float)detb * __builtin_amdgcn_rcpf(2.f * (float)p2 * p)));
-    const double p6 = 4.0 * p2 * p2 * p2;
-    opr = one_plus_r(r, p6 - detb * detb, p6);
-  }
-  double l1 = m + 2.0 * (double)p * (double)acos3_cos(r, opr);
+  // invariants of T = B + m I from those of B (tr B = 0, mu2(B) = -3 p^2)
+  const double mu2 = 3.0 * (m * m - p2);
+  const double mu3 = m * (m * m - 3.0 * p2) + detb;
+  // lambda_1 = m + y, y = 2 p c(r) the largest root of y^3 - 3 p^2 y - det B, r = det B / (2 p^3);
+  // p = 0 (a sphere) gives r = 0 and lambda_1 = m
+  const float p2f = (float)p2;
+  const float p = __builtin_amdgcn_sqrtf(p2f);
+  const float rq = (float)detb * __builtin_amdgcn_rcpf(2.f * p2f * p);
+  const float r = p2f > 0.f ? fminf(1.f, fmaxf(-1.f, rq)) : 0.f;
+  const double p6 = 4.0 * p2 * p2 * p2;
+  double y = 2.0 * (double)p * (double)acos3_cos(one_plus_r(r, p6 - detb * detb, p6));
   {
-    const double ch = ((l1 - delta) * l1 + mu2) * l1 - mu3;
-    const double chp = (3.0 * l1 - 2.0 * delta) * l1 + mu2;
-    if (chp > 1e-6 * (m * m + p2)) l1 -= ch * (double)__builtin_amdgcn_rcpf((float)chp);
+    const double ch = (y * y - 3.0 * p2) * y - detb;
+    const double chp = 3.0 * (y * y - p2);
+    const double step = ch * (double)__builtin_amdgcn_rcpf((float)chp);
+    y = chp > 1e-6 * p2 ? y - step : y;
   }
+  const double l1 = m + y;
   // collapse cubic P(F) = F^3 + a F^2 + b F + c, depressed with F = t - a/3
   const double a = -l1;
   const double b = -mu2 * (1.0 / 7.0);
@@ -222,11 +225,11 @@ __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, floa
   float t;
   if (disc < 0.0) {
     // three real roots: t = 2 sqrt(-p3) c(r_c), r_c = -hq / (-p3)^(3/2), 1 - r_c^2 = disc / p3^3
-    const float rr = __builtin_sqrtf((float)(-p3));
+    const float rr = __builtin_amdgcn_sqrtf((float)(-p3));
     const float rc = fminf(1.f, fmaxf(-1.f, (float)(-hq) * __builtin_amdgcn_rcpf(rr * rr * rr)));
-    t = 2.f * rr * acos3_cos(rc, one_plus_r(rc, disc, p3c));
+    t = 2.f * rr * acos3_cos(one_plus_r(rc, disc, p3c));
   } else {
-    const float sd = __builtin_sqrtf((float)disc);
+    const float sd = __builtin_amdgcn_sqrtf((float)disc);
     const float u = fast_cbrt((float)(-hq) - copysignf(sd, (float)hq));
     t = u != 0.f ? u - (float)p3 * __builtin_amdgcn_rcpf(u) : 0.f;
   }
@@ -234,7 +237,8 @@ __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, floa
   {
     const double f = ((x + a) * x + b) * x + c;
     const double fp = (3.0 * x + 2.0 * a) * x + b;
-    if (fp > 0.0) x -= f * (double)__builtin_amdgcn_rcpf((float)fp);
+    const double step = f * (double)__builtin_amdgcn_rcpf((float)fp);
+    x = fp > 0.0 ? x - step : x;
   }
   const float fe3 = x > 0.0 ? (float)x : 0.f;
   const float dl = (float)delta;
