@@ -178,6 +178,12 @@ struct Engine {
   static constexpr int nb(int R) { return Q * P * (N / R); }
   static constexpr int kcount(int R) { return (nb(R) + T - 1) / T; }
   static constexpr int K0 = kcount(R0);
+  // most elements a thread holds in any stage
+  static constexpr int max_held() {
+    int m = 0;
+    for (int i = 0; i < FAC.n; ++i) m = kcount(FAC.r[i]) * FAC.r[i] > m ? kcount(FAC.r[i]) * FAC.r[i] : m;
+    return m;
+  }
   static constexpr int NPAD = IL ? N : N + N / 16 + 1;
   static constexpr int LDS_ELEMS = Q * P * NPAD;
 
@@ -246,7 +252,11 @@ struct Engine {
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       if constexpr (!FIRST) {
-        const int kk = jj[k] % Ns;
+        int kk = jj[k] % Ns;
+        // Strided (interleaved) tiles: the caller runs several transforms in a loop with one
+        // transform's data live; an opaque index keeps the compiler from hoisting every stage's
+        // twiddle addresses out of that loop, which would hold ~14 more VGPRs across it.
+        if constexpr (IL) asm volatile("" : "+v"(kk));
 #pragma unroll
         for (int x = 1; x < R; ++x) a[k][x] = cmul(a[k][x], twiddle(tw, x * kk * TWS));
       }

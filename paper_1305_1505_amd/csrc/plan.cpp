@@ -79,7 +79,8 @@ void validate_desc(const pin_plan_desc* d) {
 size_t workspace_bytes(int n, int n_radii, bool fp64) {
   const size_t rb = fp64 ? 8 : 4;
   const size_t slot = (size_t)n * n * (n / 2) * 2 * rb;
-  return 11 * slot + (size_t)n * 2 * rb + (size_t)n * n_radii * rb;
+  // workspace slots, twiddles, one window row per radius plus a row of ones (no smoothing)
+  return 11 * slot + (size_t)n * 2 * rb + (size_t)n * (n_radii + 1) * rb;
 }
 
 void check_device_range(const void* p, size_t bytes, const char* name) {
@@ -117,11 +118,12 @@ pin_plan plan_create(const pin_plan_desc* desc, int radii_capacity) {
     hip_check(hipGetDevice(&p->device), "hipGetDevice");
     p->slot_bytes = (size_t)p->n * p->n * (p->n / 2) * p->complex_bytes();
     p->tw = device_alloc((size_t)p->n * p->complex_bytes(), "twiddles");
-    p->wtab = device_alloc((size_t)p->n * p->nr_capacity * p->real_bytes, "windows");
+    p->wtab = device_alloc((size_t)p->n * (p->nr_capacity + 1) * p->real_bytes, "windows");
     p->X = device_alloc(4 * p->slot_bytes, "workspace X");
     p->Y = device_alloc(6 * p->slot_bytes, "workspace Y");
     p->G = device_alloc(p->slot_bytes, "workspace G");
     upload(p->tw, twiddles(p->n), p->fp64, nullptr);
+    upload(p->window_row(p->nr_capacity), std::vector<double>((size_t)p->n, 1.0), p->fp64, nullptr);
     plan_set_radii(p, desc->radii_cells, desc->n_radii, nullptr);
   } catch (...) {
     plan_free(p);
@@ -173,7 +175,7 @@ void plan_reset(pin_plan p, void* F, uint8_t* ridx, hipStream_t s) {
 void plan_run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, int r1, hipStream_t s) {
   prep_hessian_input(p, dk, s);
   for (int r = r0; r < r1; ++r) {
-    const char* w = static_cast<const char*>(p->wtab) + (size_t)r * p->n * p->real_bytes;
+    const void* w = p->window_row(r);
     p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
     p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
     p->launch(KC_ZPASS_COLLAPSE, s, [&] { p->ops->zpass_collapse(p->Y, p->tw, F, ridx, r, p->sphere_gain, s); });
@@ -181,7 +183,7 @@ void plan_run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, 
 }
 
 void plan_deformation_tensor(pin_plan p, const void* dk, int r, void* T6, hipStream_t s) {
-  const void* w = r < 0 ? nullptr : static_cast<const char*>(p->wtab) + (size_t)r * p->n * p->real_bytes;
+  const void* w = p->window_row(r < 0 ? p->nr_capacity : r);
   prep_hessian_input(p, dk, s);
   p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
   p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
@@ -201,7 +203,8 @@ void plan_displacements(pin_plan p, const void* dk, void* psi1, void* psi2, hipS
     // mu2 of the unsmoothed tensor, forward along z (fused into the z pass), y, x; then
     // (3/7) i (L/2pi) f / f^2 and the inverse gradient transforms.
     prep_hessian_input(p, dk, s);
-    p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, nullptr, p->tw, 1.0, s); });
+    const void* ones = p->window_row(p->nr_capacity);
+    p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, ones, p->tw, 1.0, s); });
     p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
     p->launch(KC_ZPASS_MU2, s, [&] { p->ops->zpass_mu2(p->Y, p->tw, p->xslot(0), s); });
     p->launch(KC_YPASS_FWD, s, [&] { p->ops->ypass(2, p->xslot(0), p->xslot(1), p->tw, s); });

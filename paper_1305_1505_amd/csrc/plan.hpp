@@ -78,7 +78,7 @@ struct pin_plan_s {
   const pin::SizeOps* ops = nullptr;
   int device = 0;
   void* tw = nullptr;
-  void* wtab = nullptr;
+  void* wtab = nullptr;   // (nr_capacity + 1) rows of N window values
   void* X = nullptr;      // 4 half slots (= 2 packed slots)
   void* Y = nullptr;      // 6 half slots (= 3 packed slots)
   void* G = nullptr;      // 1 half slot: the radius-independent Hessian input
@@ -91,6 +91,8 @@ struct pin_plan_s {
   size_t half_spectrum_bytes() const { return (size_t)n * n * (n / 2 + 1) * complex_bytes(); }
   size_t real_field_bytes() const { return (size_t)n * n * n * real_bytes; }
   char* xslot(int i) const { return static_cast<char*>(X) + (size_t)i * slot_bytes; }
+  // window table row r (r < nr_capacity: radius r; r = nr_capacity: all ones, no smoothing)
+  void* window_row(int r) const { return static_cast<char*>(wtab) + (size_t)r * n * real_bytes; }
 
   hipEvent_t take_event();
   void recycle_events();

@@ -60,7 +60,7 @@ def test_workspace_bytes_formula():
     n, nr = 512, 40
     got = B.pin_plan_workspace_bytes(B.make_desc(n, 1000.0, [float(nr - i) for i in range(nr)]))
     slot = n * n * (n // 2) * 8
-    assert got == 11 * slot + n * 8 + n * nr * 4
+    assert got == 11 * slot + n * 8 + n * (nr + 1) * 4
 
 
 def test_status_strings():
