@@ -20,7 +20,8 @@
 //   radix-R DFT with root exp(DIR * 2 pi i / R),
 //   outputs to (j / Ns) * Ns * R + (j mod Ns) + s*Ns.
 // Twiddles come from a table of exp(2 pi i m/N), m < N, computed in float64 on the host and
-// rounded once to the transform precision (conjugated for DIR = -1).
+// rounded once to the transform precision (conjugated for DIR = -1), staged in LDS per stage
+// (load_stage_twiddles).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -93,6 +94,42 @@ constexpr int radix_prefix(const Factor& f, int s) {
   int p = 1;
   for (int i = 0; i < s; ++i) p *= f.r[i];
   return p;
+}
+
+// Twiddles of the middle and last stages, laid out per stage in LDS as
+//   [off(s) + (x - 1) * Ns + kk] = w^(x * kk * N/(Ns R)),   x in [1, R), kk in [0, Ns)
+// for stage s >= 1 (radix R, Ns = product of the earlier radices): the lanes of a butterfly row
+// read consecutive entries, free of the bank conflicts of strided reads into an N-entry table.
+constexpr int tw_stage_offset(const Factor& f, int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) off += (f.r[i] - 1) * radix_prefix(f, i);
+  return off;
+}
+constexpr int tw_elems(int N) {
+  const Factor f = factorize(N);
+  const int e = tw_stage_offset(f, f.n);
+  return e > 0 ? e : 1;
+}
+
+// Fill the per-stage table from the N-entry table exp(2 pi i m/N) in global memory (one stage
+// per instantiation, so that every index is a compile-time constant).
+template <int N, int T, int S_, typename V>
+__device__ __forceinline__ void fill_stage_twiddles(V* __restrict__ s_tw, const V* __restrict__ tw, int t) {
+  constexpr Factor f = factorize(N);
+  if constexpr (S_ < f.n) {
+    constexpr int ns = radix_prefix(f, S_), R = f.r[S_], off = tw_stage_offset(f, S_);
+    for (int i = t; i < (R - 1) * ns; i += T) {
+      const int x = i / ns + 1, kk = i % ns;
+      s_tw[off + i] = tw[x * kk * (N / (ns * R))];
+    }
+    fill_stage_twiddles<N, T, S_ + 1>(s_tw, tw, t);
+  }
+}
+
+template <int N, int T, typename V>
+__device__ __forceinline__ void load_stage_twiddles(V* __restrict__ s_tw, const V* __restrict__ tw, int t) {
+  fill_stage_twiddles<N, T, 1>(s_tw, tw, t);
+  __syncthreads();
 }
 
 constexpr bool size_ok(int n) {
@@ -222,7 +259,7 @@ struct Engine {
     constexpr int Ns = radix_prefix(FAC, s);
     constexpr int KS = kcount(R);
     constexpr int M = N / R;
-    constexpr int TWS = N / (Ns * R);
+    constexpr int TWO = tw_stage_offset(FAC, s);   // this stage's block of the twiddle table
     constexpr bool FIRST = (s == 0);
     constexpr bool LAST = (s == S - 1);
     V a[KS][R];
@@ -258,7 +295,7 @@ struct Engine {
         // twiddle addresses out of that loop, which would hold ~14 more VGPRs across it.
         if constexpr (IL) asm volatile("" : "+v"(kk));
 #pragma unroll
-        for (int x = 1; x < R; ++x) a[k][x] = cmul(a[k][x], twiddle(tw, x * kk * TWS));
+        for (int x = 1; x < R; ++x) a[k][x] = cmul(a[k][x], twiddle(tw, TWO + (x - 1) * Ns + kk));
       }
       dft<R, DIR>(a[k]);
     }

@@ -22,7 +22,7 @@
 //            real values of a point stay in registers for the per-point epilogue (collapse,
 //            store, or the 2LPT source).
 // Gradients (displacements) use the same passes with a + b + c = 1 and g = i c M dk / f^2.
-// Every kernel copies the twiddle table to LDS first.
+// Every kernel first stages the twiddles it needs in LDS, laid out per FFT stage.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -115,10 +115,17 @@ template <typename V> __device__ __forceinline__ void st_stream(V* p, V v) {
   __builtin_nontemporal_store(w, reinterpret_cast<R2*>(p));
 }
 
+// Streaming load, for the last read of a tile (its lines need not stay in L2).
+template <typename V> __device__ __forceinline__ V ld_stream(const V* p) {
+  using R = decltype(p->x);
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  const R2 w = __builtin_nontemporal_load(reinterpret_cast<const R2*>(p));
+  return V{w.x, w.y};
+}
+
 template <int N, int T, typename V>
 __device__ __forceinline__ void load_twiddles(V* __restrict__ s_tw, const V* __restrict__ tw, int t) {
-  for (int i = t; i < N; i += T) s_tw[i] = tw[i];
-  __syncthreads();
+  load_stage_twiddles<N, T>(s_tw, tw, t);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -165,7 +172,7 @@ k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
   using E = typename S::E;
   constexpr int PS = S::PS, HZ = S::HZ, NH = N / 2 + 1, NA = MODE == 0 ? 3 : 2, M = N / E::R0;
   __shared__ V lds[E::LDS_ELEMS];
-  __shared__ V s_tw[N];
+  __shared__ V s_tw[tw_elems(N)];
   const int t = threadIdx.x;
   load_twiddles<N, S::T>(s_tw, tw, t);
   const int bt = xcd_tile(blockIdx.x, S::GRID);
@@ -270,7 +277,7 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
   using EF = Engine<V, N, S::PS, 1, true, S::T, -1>;
   constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
   __shared__ V lds[E::LDS_ELEMS];
-  __shared__ V s_tw[N];
+  __shared__ V s_tw[tw_elems(N)];
   const int t = threadIdx.x;
   load_twiddles<N, S::T>(s_tw, tw, t);
   const int bt = xcd_tile(blockIdx.x, S::GRID);
@@ -355,7 +362,7 @@ k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
   constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
   constexpr size_t PSLOT = (size_t)N * N * N;
   __shared__ V lds[E::LDS_ELEMS];
-  __shared__ V s_tw[N];
+  __shared__ V s_tw[tw_elems(N)];
   const int t = threadIdx.x;
   load_twiddles<N, S::T>(s_tw, tw, t);
   const int bt = xcd_tile(blockIdx.x, S::GRID);
@@ -404,10 +411,15 @@ k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
           const R fy = R(ifreq(jv[k] + s * M, N));
           const size_t ubase = ((size_t)x * N + s * M) * HZ;   // uniform part of the address
           const unsigned off = (unsigned)(jv[k] * HZ + zv[k]);
-          const V xa = ok[k] ? in[aa * S::HSLOT + ubase + off] : V{R(0), R(0)};
+          // the last transform that reads a tile streams it (Hessian: X_1 after pair 0, X_0 and
+          // X_2 after pair 2)
+          const bool last = RC::NIN == 3 && sgn < 0 && (q == 0 || q == RC::Q - 1);
+          const V* pa = in + aa * S::HSLOT + ubase + off;
+          const V xa = ok[k] ? (last ? ld_stream(pa) : *pa) : V{R(0), R(0)};
           const V ta = cscale(xa, powf_int(fy, RC::B[ca]) * powf_int(fz, RC::C[ca]));
           if (has_b) {
-            const V xb = ab == aa ? xa : (ok[k] ? in[ab * S::HSLOT + ubase + off] : V{R(0), R(0)});
+            const V* pb = in + ab * S::HSLOT + ubase + off;
+            const V xb = ab == aa ? xa : (ok[k] ? (last ? ld_stream(pb) : *pb) : V{R(0), R(0)});
             const V tb = cscale(xb, powf_int(fy, RC::B[has_b ? cb : ca]) * powf_int(fz, RC::C[has_b ? cb : ca]));
             u[k][s] = sgn > 0 ? V{ta.x - tb.y, ta.y + tb.x} : V{ta.x + tb.y, ta.y - tb.x};
           } else {
@@ -446,7 +458,7 @@ k_ypass_fwd(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::typ
   using E = typename S::E;
   constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
   __shared__ V lds[E::LDS_ELEMS];
-  __shared__ V s_tw[N];
+  __shared__ V s_tw[tw_elems(N)];
   const int t = threadIdx.x;
   load_twiddles<N, S::T>(s_tw, tw, t);
   const int bt = xcd_tile(blockIdx.x, S::GRID);
@@ -512,7 +524,7 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
   constexpr int P = Z::P, HZ = Z::HZ, R0 = E::R0, M0 = N / R0;
   constexpr size_t PSLOT = (size_t)N * N * N;
   __shared__ V lds[E::LDS_ELEMS];
-  __shared__ V s_tw[N];
+  __shared__ V s_tw[tw_elems(N)];
   const int t = threadIdx.x;
   load_twiddles<N, Z::T>(s_tw, tw, t);
   // thread t owns pencil position (p, j) of every transform q
