@@ -1,0 +1,205 @@
+"""The benchmark-size workloads (256^3, 512^3 and 768^3, float32) in the launch configuration that
+bench.py times -- one plan, pin_generate_field, then pin_collapse_times / pin_displacements on
+the field it produced -- checked against the FP64 oracle:
+
+* the whole field, mode by mode (the oracle generates it in full);
+* F_max, R_max, the deformation tensor and psi1 at sampled grid points, by direct summation of
+  the inverse DFT at those points (oracle.points);
+* invariants that hold at any size: F >= 0 and finite, R_max in range and 255 exactly where
+  F = 0, radius-range splitting bit-identical to one call, psi2 a gradient field.
+
+Sample points are fixed corners and Nyquist-adjacent indices plus seeded random ones; nothing
+the oracle sees comes from the GPU.
+
+Tolerances (float32 FFTs, float64-computed twiddles): intermediate fields carry an absolute
+error of a few eps32 * log2(N) of their RMS; a collapse time F ~ lambda_1 inherits it.  Per
+point, |dT| <= 2e-5 sigma_T and |dF| <= 1e-4 sigma_T(R_min), sigma_T = RMS of one tensor
+component, taken from the oracle field by Parseval; R_max may differ only where the oracle's F
+at the GPU's radius is within that tolerance of its maximum.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import field, hessian, points
+from paper_1305_1505_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = ["c256_fp32", "c512_fp32", "c768_fp32"]
+N_RANDOM = {"c256_fp32": 3, "c512_fp32": 1, "c768_fp32": 0}
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_field(name):
+    cfg = W.CONFIGS[name]
+    print(f"[fullsize] oracle field {name}", flush=True)
+    return field.linear_field(cfg["seed"], cfg["n"], cfg["box"], W.SIGMA8, W.GAMMA, W.NS)
+
+
+def sample_points(name, salt):
+    """Corners and Nyquist-adjacent indices, then seeded random points."""
+    n = W.CONFIGS[name]["n"]
+    rng = np.random.default_rng(W.CONFIGS[name]["seed"] * 10 + salt)
+    fixed = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, n // 2 - 1, n // 2 + 1)]
+    return fixed + [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(N_RANDOM[name])]
+
+
+def sigma_component(dk, radius):
+    """RMS over the grid of the smoothed density (the trace of T) / sqrt(3): Parseval on the
+    half spectrum, (1/N^6) sum over the full spectrum of |W M dk|^2."""
+    n = dk.shape[0]
+    w = hessian.gaussian_window(n, radius) * hessian.nyquist_mask(n)
+    wl = np.full(n // 2 + 1, 2.0)
+    wl[0] = wl[n // 2] = 1.0
+    tot = 0.0
+    for i in range(n):
+        tot += float(np.sum(wl[None, :] * np.abs(w[i] * dk[i]) ** 2))
+    return np.sqrt(tot) / float(n) ** 3 / np.sqrt(3.0)
+
+
+def _plan(lib, name):
+    cfg = W.CONFIGS[name]
+    return lib.Plan(cfg["n"], cfg["box"], W.config_radii(cfg), sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS,
+                    prec=lib.PIN_FP32)
+
+
+def _at(t, pts):
+    """Values of a (..., N, N, N) device tensor at the points, as float64 on the host."""
+    import torch
+
+    idx = torch.tensor(pts, device=t.device, dtype=torch.long)
+    out = t[..., idx[:, 0], idx[:, 1], idx[:, 2]]
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", CONFIGS)
+def test_fullsize_field(lib, name):
+    import torch
+
+    cfg = W.CONFIGS[name]
+    n = cfg["n"]
+    ref = oracle_field(name)
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    torch.cuda.synchronize()
+    big = np.max(np.abs(ref))
+    for i0 in range(0, n, 64):
+        g = dk[i0:i0 + 64].cpu().numpy().astype(np.complex128)
+        r = ref[i0:i0 + 64]
+        # one rounding of the float64 value to float32, per component
+        for part in (np.real, np.imag):
+            err = np.abs(part(g) - part(r))
+            assert np.all(err <= 2.0 ** -23 * np.abs(part(r)) + 1e-12 * big), f"{name} rows {i0}"
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", CONFIGS)
+def test_fullsize_collapse_at_points(lib, name):
+    cfg = W.CONFIGS[name]
+    n = cfg["n"]
+    radii = W.config_radii(cfg)
+    ref_dk = oracle_field(name)
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    F, R = plan.collapse_times(dk)
+    pts = sample_points(name, 0)
+    f_gpu = _at(F, pts)
+    r_gpu = _at(R, pts).astype(np.int64)
+    print(f"[fullsize] oracle collapse at {len(pts)} points, {name}", flush=True)
+    fmax, ridx, fr = points.collapse_times_at_points(ref_dk, pts, radii)
+    tol = 1e-4 * sigma_component(ref_dk, radii[-1])
+    print(f"[fullsize] {name}: max |dF| / tol = {np.max(np.abs(f_gpu - fmax)) / tol:.3g}, "
+          f"R_max differs at {int(np.sum(r_gpu != ridx))} of {len(pts)}", flush=True)
+    for p in range(len(pts)):
+        assert abs(f_gpu[p] - fmax[p]) <= tol, f"{name} point {pts[p]}: {f_gpu[p]} vs {fmax[p]}"
+        if r_gpu[p] != ridx[p]:
+            assert r_gpu[p] != 255 and abs(fr[p, r_gpu[p]] - fmax[p]) <= tol, f"{name} point {pts[p]} radius"
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", CONFIGS)
+def test_fullsize_tensor_at_points(lib, name):
+    cfg = W.CONFIGS[name]
+    n = cfg["n"]
+    radii = W.config_radii(cfg)
+    ref_dk = oracle_field(name)
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    pts = sample_points(name, 1)
+    rsel = [0, len(radii) - 1]
+    print(f"[fullsize] oracle tensor at {len(pts)} points, {name}", flush=True)
+    ref = points.tensor_at_points(ref_dk, pts, [radii[r] for r in rsel])
+    for k, r in enumerate(rsel):
+        t6 = plan.deformation_tensor(dk, r)
+        got = _at(t6, pts).T                                     # (P, 6)
+        del t6
+        tol = 2e-5 * sigma_component(ref_dk, radii[r])
+        print(f"[fullsize] {name} radius {r}: max |dT| / tol = {np.max(np.abs(got - ref[:, k, :])) / tol:.3g}",
+              flush=True)
+        assert np.max(np.abs(got - ref[:, k, :])) <= tol, f"{name} radius {r}"
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", CONFIGS)
+def test_fullsize_za_at_points(lib, name):
+    cfg = W.CONFIGS[name]
+    n, box = cfg["n"], cfg["box"]
+    ref_dk = oracle_field(name)
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    p1, _ = plan.displacements(dk, want_psi2=False)
+    pts = sample_points(name, 2)
+    got = _at(p1, pts).T                                         # (P, 3)
+    print(f"[fullsize] oracle psi1 at {len(pts)} points, {name}", flush=True)
+    ref = points.za_at_points(ref_dk, pts, box)
+    # psi1 ~ delta / k: its RMS is dominated by the largest scales; 2e-5 of the largest sampled
+    # component with an absolute floor of 2e-5 Mpc/h
+    tol = 2e-5 * max(np.max(np.abs(ref)), 1.0)
+    print(f"[fullsize] {name}: max |dpsi1| / tol = {np.max(np.abs(got - ref)) / tol:.3g}", flush=True)
+    assert np.max(np.abs(got - ref)) <= tol
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["c512_fp32"])
+def test_fullsize_invariants(lib, name):
+    import torch
+
+    cfg = W.CONFIGS[name]
+    n = cfg["n"]
+    nr = len(W.config_radii(cfg))
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    F, R = plan.collapse_times(dk)
+    assert bool(torch.isfinite(F).all()) and float(F.min()) >= 0.0
+    never = R == 255
+    assert bool(((R < nr) | never).all())
+    assert bool(((F == 0) == never).all())
+    # radius-range splitting reproduces the one-shot result bit for bit
+    F2 = torch.empty_like(F)
+    R2 = torch.empty_like(R)
+    plan.collapse_reset(F2, R2)
+    for r0, r1 in ((0, 13), (13, 14), (14, nr)):
+        plan.collapse_times_range(dk, F2, R2, r0, r1)
+    assert bool(torch.equal(F, F2)) and bool(torch.equal(R, R2))
+    del F, R, F2, R2
+    # psi2 is a gradient: its spectrum is parallel to k (cross product ~ float32 rounding)
+    _, p2 = plan.displacements(dk, want_psi1=False)
+    spec = [np.fft.rfftn(p2[a].double().cpu().numpy()) for a in range(3)]
+    del p2
+    fx, fy, fz = hessian.freq_grids(n)
+    cross = (np.abs(fy * spec[2] - fz * spec[1]) ** 2 + np.abs(fz * spec[0] - fx * spec[2]) ** 2
+             + np.abs(fx * spec[1] - fy * spec[0]) ** 2)
+    norm = np.sqrt(fx ** 2 + fy ** 2 + fz ** 2) ** 2 * sum(np.abs(s) ** 2 for s in spec)
+    ratio = np.sqrt(np.sum(cross) / np.sum(norm))
+    print(f"[fullsize] {name}: |k x psi2~| / (|k| |psi2~|) = {ratio:.3g}", flush=True)
+    assert ratio <= 1e-5
+    plan.close()
