@@ -271,13 +271,36 @@ def main():
                                if algorithmic_bytes(k, n, real_bytes) else None)}
                   for k, v in kernels.items()}
 
-    # collapse-only rate (HIP events around pin_collapse_times)
+    # the path's parts on their own (HIP events on the plan's stream, which is torch's current
+    # stream here): collapse times as the median of 5 runs after 2 warm-ups, the field and the
+    # displacements once each
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    B.pin_collapse_times(plan.handle, dk.data_ptr(), F.data_ptr(), R.data_ptr(), stream)
-    ev1.record()
-    torch.cuda.synchronize()
-    collapse_ms = ev0.elapsed_time(ev1)
+
+    def timed(fn):
+        ev0.record()
+        fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
+    def collapse():
+        B.pin_collapse_times(plan.handle, dk.data_ptr(), F.data_ptr(), R.data_ptr(), stream)
+
+    for _ in range(2):
+        collapse()
+    runs = sorted(timed(collapse) for _ in range(5))
+    collapse_ms = runs[2]
+    field_ms = timed(lambda: B.pin_generate_field(plan.handle, seed, dk.data_ptr(), stream))
+    disp_ms = timed(lambda: B.pin_displacements(plan.handle, dk.data_ptr(), p1.data_ptr(), p2.data_ptr(), stream))
+    # whole-path roofline at the collapse-only rate: algorithmic bytes per grid-point x radius
+    # update of these passes (19 workspace slots of 4 B per point plus F read/write and the
+    # index) and the floor of any out-of-core 3D FFT design (spectrum once, one 3-component
+    # transpose round trip, F and index: 7 slots + 10 B)
+    slot_pp = 2 * real_bytes * (n // 2) / n   # workspace slot bytes per grid point
+    per_update = {"three_pass": 19 * slot_pp + 2 * real_bytes + 1, "floor": 7 * slot_pp + 2 * real_bytes + 2}
+    rate = updates / (collapse_ms * 1e-3)
+    path_roofline = {k: {"bytes_per_update": round(v, 2), "GB/s": round(rate * v / 1e9, 1),
+                         "frac": round(rate * v / 1e9 / HBM_PEAK_GBS, 4)} for k, v in per_update.items()}
     del p1, p2, F, R, dk
     plan.close()
     torch.cuda.empty_cache()
@@ -336,7 +359,10 @@ def main():
         "config": {"workload": f"{n}^3 grid, {box:g} Mpc/h, {len(radii)} Gaussian radii "
                                f"{cfg['r_max']:g}->{cfg['r_min']:g} cells, field + collapse + ZA/2LPT",
                    "n": n, "box_mpc_h": box, "n_radii": len(radii), "precision": cfg["prec"]},
-        "collapse_only": {"updates_per_s": updates / (collapse_ms * 1e-3), "ms": round(collapse_ms, 2)},
+        "collapse_only": {"updates_per_s": rate, "ms": round(collapse_ms, 2), "runs_ms": [round(x, 2) for x in runs]},
+        "field_ms": round(field_ms, 3),
+        "displacements_ms": round(disp_ms, 3),
+        "path_roofline": path_roofline,
         "fp64": fp64,
         "roofline": roofline,
         "kernels": per_kernel,
