@@ -539,30 +539,33 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
   if constexpr (EPI == EPI_COLLAPSE) {
     const R* F = static_cast<const R*>(args.F);
 #pragma unroll
-    for (int s = 0; s < R0; ++s) fold[s] = line_ok ? F[(size_t)line * N + j + s * M0] : R(0);
+    for (int s = 0; s < R0; ++s) fold[s] = F[(size_t)(line_ok ? line : Z::LINES - 1) * N + j + s * M0];
   }
+  // Packed storage of C[n]: P[n] for n < N/2, P[3N/2 - n] for n > N/2; R0 is even, so elements
+  // s < R0/2 are the first kind and s >= R0/2 the second.  Loads are unconditional (a wave past
+  // the last line reads the last line and stores nothing); the Nyquist element n = N/2 (lane
+  // j = 0, s = R0/2) reads P[N/2], which is never written, and is replaced by zero.
+  static_assert(R0 % 2 == 0 && M0 * (R0 / 2) == HZ, "z pass: the first half of the elements is n < N/2");
+  const int lineL = line_ok ? line : Z::LINES - 1;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const V* src = in + (size_t)q * PSLOT + (size_t)line * N;
+    const V* src = in + (size_t)q * PSLOT + (size_t)lineL * N;
+    const V* lo = src + j;
+    const V* hi = src + (3 * HZ - j);
 #pragma unroll
-    for (int s = 0; s < R0; ++s) {
-      const int n = j + s * M0;
-      const int idx = n < HZ ? n : 3 * HZ - n;   // packed storage of C[n]
-      v[q][s] = (line_ok && n != HZ) ? src[idx] : V{R(0), R(0)};
+    for (int s = 0; s < R0 / 2; ++s) v[q][s] = lo[s * M0];
+    {
+      const V x = src[j == 0 ? HZ : N - j];
+      v[q][R0 / 2] = j == 0 ? V{R(0), R(0)} : x;
     }
+#pragma unroll
+    for (int s = R0 / 2 + 1; s < R0; ++s) v[q][s] = hi[-s * M0];
   }
   if constexpr (Z::ZT::QL == Q) {
     E::run(v, lds, s_tw, t);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      V w[1][R0];
-#pragma unroll
-      for (int s = 0; s < R0; ++s) w[0][s] = v[q][s];
-      E::run(w, lds, s_tw, t);
-#pragma unroll
-      for (int s = 0; s < R0; ++s) v[q][s] = w[0][s];
-    }
+    for (int q = 0; q < Q; ++q) E::run(*reinterpret_cast<V(*)[1][R0]>(&v[q]), lds, s_tw, t);
   }
   // v[q][s] = (packed component 2q) + i (packed component 2q+1) at n = j + s*M0 of line `line`;
   // comp(c, s) is the canonical component c (Hessian xx xy xz yy yz zz; gradient x y z).
