@@ -76,6 +76,36 @@ def grouped_tensor_sums(dk, points):
     return sums
 
 
+def grouped_gradient_sums(dk, points):
+    """G[p, a, m] = sum over modes with |f|^2 = m of w_l Re(i f_a / f^2 M dk e^{2 pi i f.q_p/N});
+    shape (P, 3, 3 (N/2)^2 + 1)."""
+    n = dk.shape[0]
+    npts = len(points)
+    f = int_freqs(n)
+    fy = f[:, None]
+    fz = np.arange(n // 2 + 1, dtype=np.float64)[None, :]
+    mmax = 3 * (n // 2) ** 2
+    ex, ey, ez = _phase_rows(n, points)
+    wl = _half_weights(n)[None, :]
+    sums = np.zeros((npts, 3, mmax + 1))
+    eyz = [ey[p][:, None] * ez[p][None, :] for p in range(npts)]
+    half = n // 2
+    for i in range(n):
+        fx = f[i]
+        f2 = fx * fx + fy * fy + fz * fz
+        mask = (abs(fx) != half) & (np.abs(fy) != half) & (fz != half) & (f2 > 0)
+        inv = np.where(mask, 1.0 / np.where(f2 > 0, f2, 1.0), 0.0)
+        g = 1j * dk[i] * inv * wl
+        m = f2.astype(np.int64).ravel()
+        fvec = (np.full_like(f2, fx).ravel(), np.broadcast_to(fy, f2.shape).ravel(),
+                np.broadcast_to(fz, f2.shape).ravel())
+        for p in range(npts):
+            term = (g * (ex[p, i] * eyz[p])).ravel()
+            for a in range(3):
+                sums[p, a] += np.bincount(m, weights=np.real(fvec[a] * term), minlength=mmax + 1)
+    return sums
+
+
 def tensor_at_points(dk, points, radii_cells):
     """T_ab at each point for each radius (None: no smoothing); shape (P, n_radii, 6)."""
     n = dk.shape[0]
@@ -100,6 +130,21 @@ def collapse_times_at_points(dk, points, radii_cells):
         fmax = np.where(up, f[:, r], fmax)
         ridx = np.where(up, np.uint8(r), ridx)
     return fmax, ridx, f
+
+
+def collapse_times_with_velocity_at_points(dk, points, radii_cells, box):
+    """As collapse_times_at_points, plus v_max (P, 3) in Mpc/h: the ZA displacement smoothed on
+    the radius of the last update of F_max (0 where none), as ``run.collapse_times_with_velocity``."""
+    n = dk.shape[0]
+    fmax, ridx, f = collapse_times_at_points(dk, points, radii_cells)
+    g = grouped_gradient_sums(dk, points)
+    m = np.arange(g.shape[2], dtype=np.float64)
+    vmax = np.zeros((len(points), 3))
+    for p in range(len(points)):
+        if ridx[p] != NEVER:
+            w = np.exp(-0.5 * (2.0 * np.pi * radii_cells[ridx[p]] / n) ** 2 * m)
+            vmax[p] = (g[p] @ w) * (box / (2.0 * np.pi)) / float(n) ** 3
+    return fmax, ridx, vmax, f
 
 
 def za_at_points(dk, points, box):

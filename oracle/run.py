@@ -5,6 +5,12 @@ trajectory, F_max, and the smoothing scale R_max where it was reached.  Readings
 visited from the largest to the smallest; F_max starts at 0 and the radius index at 255 ("never
 collapsed"); an update needs a strictly larger F, so ties keep the larger radius.
 
+Velocity at the trajectory maximum (section "Collapse times", last paragraph): with F_max the
+code records v_max, computed from the first derivative of the peculiar potential smoothed on
+R_max each time F_max is updated.  Reading: v_max is the Zel'dovich displacement of the field
+smoothed on that radius, psi1_R(k) = i k W(kR) dk / k^2 in Mpc/h at D = 1 (the peculiar velocity
+is a H f D times it, a factor per output time outside this path); 0 where F_max was never set.
+
 Displacements (sections on fragmentation and on the code, and the 2LPT extension in the
 conclusions): the Zel'dovich displacement psi1 = -grad(phi) at D = 1, i.e. psi1(k) = i k dk / k^2,
 so that -div(psi1) = delta; and the second-order displacement of standard EdS 2LPT,
@@ -36,6 +42,23 @@ def collapse_times(dk, radii_cells, r_begin=0, r_end=None, fmax=None, ridx=None)
         fmax = np.where(up, f, fmax)
         ridx = np.where(up, np.uint8(r), ridx)
     return fmax, ridx
+
+
+def collapse_times_with_velocity(dk, radii_cells, box):
+    """(F_max, R_max index, v_max (3, N, N, N) in Mpc/h): v_max is the smoothed ZA displacement
+    at the radius of the last update of F_max, 0 where there was none."""
+    n = dk.shape[0]
+    fmax = np.zeros((n, n, n), dtype=np.float64)
+    ridx = np.full((n, n, n), NEVER, dtype=np.uint8)
+    vmax = np.zeros((3, n, n, n), dtype=np.float64)
+    for r, radius in enumerate(radii_cells):
+        f = collapse.inverse_collapse_time(hessian.deformation_tensor(dk, radius))
+        up = f > fmax
+        fmax = np.where(up, f, fmax)
+        ridx = np.where(up, np.uint8(r), ridx)
+        v = _gradient_fields(dk * hessian.gaussian_window(n, radius), box)
+        vmax = np.where(up[None], v, vmax)
+    return fmax, ridx, vmax
 
 
 def per_radius_F(dk, radius_cells):
