@@ -291,6 +291,15 @@ def main():
     runs = sorted(timed(collapse) for _ in range(5))
     collapse_ms = runs[2]
     field_ms = timed(lambda: B.pin_generate_field(plan.handle, seed, dk.data_ptr(), stream))
+    # collapse times with the velocity at the trajectory maximum (v_max), after one warm-up
+    vmax = torch.empty((3, n, n, n), dtype=plan.real, device="cuda")
+
+    def collapse_v():
+        B.pin_collapse_times_v(plan.handle, dk.data_ptr(), F.data_ptr(), R.data_ptr(), vmax.data_ptr(), stream)
+
+    collapse_v()
+    vel_ms = timed(collapse_v)
+    del vmax
     disp_ms = timed(lambda: B.pin_displacements(plan.handle, dk.data_ptr(), p1.data_ptr(), p2.data_ptr(), stream))
     # whole-path roofline at the collapse-only rate: algorithmic bytes per grid-point x radius
     # update of these passes (19 workspace slots of 4 B per point plus F read/write and the
@@ -360,6 +369,7 @@ def main():
                                f"{cfg['r_max']:g}->{cfg['r_min']:g} cells, field + collapse + ZA/2LPT",
                    "n": n, "box_mpc_h": box, "n_radii": len(radii), "precision": cfg["prec"]},
         "collapse_only": {"updates_per_s": rate, "ms": round(collapse_ms, 2), "runs_ms": [round(x, 2) for x in runs]},
+        "collapse_with_velocity": {"updates_per_s": updates / (vel_ms * 1e-3), "ms": round(vel_ms, 2)},
         "field_ms": round(field_ms, 3),
         "displacements_ms": round(disp_ms, 3),
         "path_roofline": path_roofline,

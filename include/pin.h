@@ -123,6 +123,24 @@ pin_status pin_collapse_times_range(pin_plan plan, const void* dk, void* F, uint
 pin_status pin_collapse_times(pin_plan plan, const void* dk, void* F, uint8_t* ridx,
                               hipStream_t stream);
 
+/* Velocity at the trajectory maximum (section "Collapse times", last paragraph: with F_max the
+ * code records v_max, computed from the first derivative of the peculiar potential smoothed on
+ * R_max each time F_max is updated).  v_max is [3][N^3] (x, y, z; plan precision, device,
+ * caller-owned): the Zel'dovich displacement of the field smoothed on the radius of the last
+ * update of F_max, psi1_R(k) = i k W(kR) dk / k^2 in Mpc/h at D = 1 (times a H f D for a
+ * peculiar velocity), 0 where F_max was never set.  F and ridx are exactly those of the calls
+ * without _v.  The first _v call on a plan allocates pin_plan_velocity_workspace_bytes of
+ * device memory more, kept until pin_plan_destroy. */
+pin_status pin_plan_velocity_workspace_bytes(const pin_plan_desc* desc, size_t* bytes);
+/* pin_collapse_reset, and v_max <- 0. */
+pin_status pin_collapse_reset_v(pin_plan plan, void* F, uint8_t* ridx, void* vmax, hipStream_t stream);
+/* pin_collapse_times_range, also setting v_max[.][q] wherever F[q] is updated. */
+pin_status pin_collapse_times_range_v(pin_plan plan, const void* dk, void* F, uint8_t* ridx, void* vmax,
+                                      int r_begin, int r_end, hipStream_t stream);
+/* pin_collapse_reset_v followed by pin_collapse_times_range_v over all radii. */
+pin_status pin_collapse_times_v(pin_plan plan, const void* dk, void* F, uint8_t* ridx, void* vmax,
+                                hipStream_t stream);
+
 /* The six deformation-tensor components at radius index r (r = -1: unsmoothed), written to T6
  * (device, [6][N][N][N] real, order xx, xy, xz, yy, yz, zz). */
 pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6,

@@ -60,6 +60,10 @@ _sig = {
     "pin_collapse_times_range": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "pin_collapse_times": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pin_deformation_tensor": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
+    "pin_plan_velocity_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "pin_collapse_reset_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pin_collapse_times_range_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "pin_collapse_times_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pin_displacements": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
@@ -132,6 +136,25 @@ def pin_collapse_times_range(plan, dk, F, ridx, r_begin, r_end, stream=0):
 
 def pin_collapse_times(plan, dk, F, ridx, stream=0):
     _check(lib.pin_collapse_times(plan, _vp(dk), _vp(F), _vp(ridx), _vp(stream)))
+
+
+def pin_plan_velocity_workspace_bytes(desc):
+    out = ctypes.c_size_t(0)
+    _check(lib.pin_plan_velocity_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def pin_collapse_reset_v(plan, F, ridx, vmax, stream=0):
+    _check(lib.pin_collapse_reset_v(plan, _vp(F), _vp(ridx), _vp(vmax), _vp(stream)))
+
+
+def pin_collapse_times_range_v(plan, dk, F, ridx, vmax, r_begin, r_end, stream=0):
+    _check(lib.pin_collapse_times_range_v(plan, _vp(dk), _vp(F), _vp(ridx), _vp(vmax), int(r_begin), int(r_end),
+                                          _vp(stream)))
+
+
+def pin_collapse_times_v(plan, dk, F, ridx, vmax, stream=0):
+    _check(lib.pin_collapse_times_v(plan, _vp(dk), _vp(F), _vp(ridx), _vp(vmax), _vp(stream)))
 
 
 def pin_deformation_tensor(plan, dk, r, T6, stream=0):
@@ -235,6 +258,25 @@ class Plan:
         pin_collapse_times_range(self.handle, dk.data_ptr(), F.data_ptr(), ridx.data_ptr(), r_begin, r_end,
                                  self._stream())
         return F, ridx
+
+    def collapse_times_v(self, dk, F=None, ridx=None, vmax=None):
+        """(F_max, R_max index, v_max [3, N, N, N]) -- pin_collapse_times_v."""
+        n = self.n
+        dk = self._as_spectrum(dk)
+        F = self.torch.empty((n, n, n), dtype=self.real, device="cuda") if F is None else F
+        ridx = self.torch.empty((n, n, n), dtype=self.torch.uint8, device="cuda") if ridx is None else ridx
+        vmax = self.torch.empty((3, n, n, n), dtype=self.real, device="cuda") if vmax is None else vmax
+        pin_collapse_times_v(self.handle, dk.data_ptr(), F.data_ptr(), ridx.data_ptr(), vmax.data_ptr(), self._stream())
+        return F, ridx, vmax
+
+    def collapse_reset_v(self, F, ridx, vmax):
+        pin_collapse_reset_v(self.handle, F.data_ptr(), ridx.data_ptr(), vmax.data_ptr(), self._stream())
+
+    def collapse_times_range_v(self, dk, F, ridx, vmax, r_begin, r_end):
+        dk = self._as_spectrum(dk)
+        pin_collapse_times_range_v(self.handle, dk.data_ptr(), F.data_ptr(), ridx.data_ptr(), vmax.data_ptr(),
+                                   r_begin, r_end, self._stream())
+        return F, ridx, vmax
 
     def deformation_tensor(self, dk, r):
         n = self.n

@@ -99,6 +99,47 @@ pin_status pin_collapse_times(pin_plan plan, const void* dk, void* F, uint8_t* r
   });
 }
 
+pin_status pin_plan_velocity_workspace_bytes(const pin_plan_desc* desc, size_t* bytes) {
+  return guarded([&] {
+    validate_desc(desc);
+    if (bytes == nullptr) fail(PIN_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = velocity_workspace_bytes(desc->n, desc->prec == PIN_FP64);
+  });
+}
+
+pin_status pin_collapse_reset_v(pin_plan plan, void* F, uint8_t* ridx, void* vmax, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    check_field_outputs(plan, F, ridx);
+    check_device_range(vmax, 3 * plan->real_field_bytes(), "vmax");
+    plan_reset_v(plan, F, ridx, vmax, stream);
+  });
+}
+
+pin_status pin_collapse_times_range_v(pin_plan plan, const void* dk, void* F, uint8_t* ridx, void* vmax, int r_begin,
+                                      int r_end, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (r_begin < 0 || r_end > plan->nr || r_begin >= r_end)
+      fail(PIN_ERR_INVALID_ARG, "radius range must satisfy 0 <= r_begin < r_end <= n_radii");
+    check_device_range(dk, plan->half_spectrum_bytes(), "dk");
+    check_field_outputs(plan, F, ridx);
+    check_device_range(vmax, 3 * plan->real_field_bytes(), "vmax");
+    plan_run_radii_v(plan, dk, F, ridx, vmax, r_begin, r_end, stream);
+  });
+}
+
+pin_status pin_collapse_times_v(pin_plan plan, const void* dk, void* F, uint8_t* ridx, void* vmax, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    check_device_range(dk, plan->half_spectrum_bytes(), "dk");
+    check_field_outputs(plan, F, ridx);
+    check_device_range(vmax, 3 * plan->real_field_bytes(), "vmax");
+    plan_reset_v(plan, F, ridx, vmax, stream);
+    plan_run_radii_v(plan, dk, F, ridx, vmax, 0, plan->nr, stream);
+  });
+}
+
 pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6, hipStream_t stream) {
   return guarded([&] {
     check_plan(plan);

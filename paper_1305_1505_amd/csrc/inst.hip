@@ -53,6 +53,10 @@ void ypass(int recipe, const void* in, void* out, const void* tw, hipStream_t s)
     using S = Strided<RR, NN, +1>;
     hipLaunchKernelGGL((k_ypass_packed<RR, NN, 1>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
                        static_cast<VV*>(out), static_cast<const VV*>(tw));
+  } else if (recipe == 3) {
+    using S = Strided<RR, NN, +1>;
+    hipLaunchKernelGGL((k_ypass_packed<RR, NN, 3>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw));
   } else {
     using S = Strided<RR, NN, -1>;
     hipLaunchKernelGGL((k_ypass_fwd<RR, NN>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
@@ -68,6 +72,21 @@ void zpass_collapse(const void* in, const void* tw, void* F, uint8_t* ridx, int 
   a.r = r;
   a.cc.sphere_gain = sphere_gain;
   hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_COLLAPSE>), dim3(Z::GRID), dim3(Z::T), 0, s,
+                     static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
+}
+
+void zpass_collapse_v(const void* in, const void* gin, const void* tw, void* F, uint8_t* ridx, void* vmax, int r,
+                      double sphere_gain, double vscale, hipStream_t s) {
+  using Z = ZPass<RR, NN, 3, EPI_COLLAPSE_V>;
+  ZArgs a{};
+  a.F = F;
+  a.ridx = ridx;
+  a.r = r;
+  a.cc.sphere_gain = sphere_gain;
+  a.gin = gin;
+  a.vout = vmax;
+  a.vscale = vscale;
+  hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_COLLAPSE_V>), dim3(Z::GRID), dim3(Z::T), 0, s,
                      static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
 }
 
@@ -109,6 +128,13 @@ void reset(void* F, uint8_t* ridx, hipStream_t s) {
   hipLaunchKernelGGL((k_reset<RR>), dim3(grid), dim3(block), 0, s, static_cast<RR*>(F), ridx, total);
 }
 
+void zero(void* p, size_t count, hipStream_t s) {
+  if (count == 0) return;
+  const int block = 256;
+  const int grid = (int)((count + block - 1) / block);
+  hipLaunchKernelGGL((k_zero<RR>), dim3(grid), dim3(block), 0, s, static_cast<RR*>(p), count);
+}
+
 void collapse_points(const void* t6, size_t count, void* F, double sphere_gain, hipStream_t s) {
   if (count == 0) return;
   CollapseConst cc{sphere_gain};
@@ -125,7 +151,8 @@ void collapse_points(const void* t6, size_t count, void* F, double sphere_gain, 
 
 const SizeOps* PIN_CAT(ops_, PIN_INST_FP64, PIN_INST_N)() {
   static const SizeOps ops = {
-      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, ypass, zpass_collapse, zpass_store, zpass_mu2, grf, reset, collapse_points,
+      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, ypass, zpass_collapse, zpass_collapse_v, zpass_store,
+      zpass_mu2, grf, reset, zero, collapse_points,
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{ZPass<RR, NN, 3, EPI_COLLAPSE>::GRID, ZPass<RR, NN, 3, EPI_COLLAPSE>::T}};

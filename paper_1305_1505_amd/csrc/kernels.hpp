@@ -338,16 +338,22 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
 //   Hessian (RECIPE 0), packed order xy xz | yy yz | xx zz:
 //       (1,1,0) (1,0,1) | (0,2,0) (0,1,1) | (2,0,0) (0,0,2)
 //   gradient (RECIPE 1), packed order x y | z:  (1,0,0) (0,1,0) | (0,0,1)
-// hessian_component / gradient_component map the packed order back to (xx, xy, xz, yy, yz, zz)
-// and (x, y, z).
+//   gradient of the Hessian's x-pass outputs (RECIPE 3, v_max): RECIPE 1's components times i,
+//       which the gradient x pass applies itself but the Hessian x pass does not (TI)
+// The z pass maps the packed order back to (xx, xy, xz, yy, yz, zz) and (x, y, z).
 template <int RECIPE> struct YRecipe;
 template <> struct YRecipe<0> {
+  static constexpr bool TI = false;
   static constexpr int NIN = 3, NC = 6, Q = 3;
   static constexpr int A[6] = {1, 1, 0, 0, 2, 0}, B[6] = {1, 0, 2, 1, 0, 0}, C[6] = {0, 1, 0, 1, 0, 2};
 };
 template <> struct YRecipe<1> {
+  static constexpr bool TI = false;
   static constexpr int NIN = 2, NC = 3, Q = 2;
   static constexpr int A[3] = {1, 0, 0}, B[3] = {0, 1, 0}, C[3] = {0, 0, 1};
+};
+template <> struct YRecipe<3> : YRecipe<1> {
+  static constexpr bool TI = true;
 };
 
 template <typename R, int N, int RECIPE>
@@ -416,11 +422,13 @@ k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
           const bool last = RC::NIN == 3 && sgn < 0 && (q == 0 || q == RC::Q - 1);
           const V* pa = in + aa * S::HSLOT + ubase + off;
           const V xa = ok[k] ? (last ? ld_stream(pa) : *pa) : V{R(0), R(0)};
-          const V ta = cscale(xa, powf_int(fy, RC::B[ca]) * powf_int(fz, RC::C[ca]));
+          V ta = cscale(xa, powf_int(fy, RC::B[ca]) * powf_int(fz, RC::C[ca]));
+          if constexpr (RC::TI) ta = V{-ta.y, ta.x};
           if (has_b) {
             const V* pb = in + ab * S::HSLOT + ubase + off;
             const V xb = ab == aa ? xa : (ok[k] ? (last ? ld_stream(pb) : *pb) : V{R(0), R(0)});
-            const V tb = cscale(xb, powf_int(fy, RC::B[has_b ? cb : ca]) * powf_int(fz, RC::C[has_b ? cb : ca]));
+            V tb = cscale(xb, powf_int(fy, RC::B[has_b ? cb : ca]) * powf_int(fz, RC::C[has_b ? cb : ca]));
+            if constexpr (RC::TI) tb = V{-tb.y, tb.x};
             u[k][s] = sgn > 0 ? V{ta.x - tb.y, ta.y + tb.x} : V{ta.x + tb.y, ta.y - tb.x};
           } else {
             u[k][s] = ta;
@@ -491,7 +499,7 @@ k_ypass_fwd(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::typ
 // ---------------------------------------------------------------------------------------------
 // z pass: inverse transform along z of Q packed slots (two real components each) and the
 // per-point epilogue.
-enum ZEpi { EPI_COLLAPSE = 0, EPI_STORE = 1, EPI_MU2 = 2 };
+enum ZEpi { EPI_COLLAPSE = 0, EPI_STORE = 1, EPI_MU2 = 2, EPI_COLLAPSE_V = 3 };
 
 template <typename R, int N, int Q, int EPI>
 struct ZPass {
@@ -513,6 +521,9 @@ struct ZArgs {
   int nc;           // EPI_STORE: number of real components to store (<= 2Q)
   void* out;        // EPI_STORE: [nc][N^3] real; EPI_MU2: one half slot (complex)
   CollapseConst cc;
+  const void* gin;  // EPI_COLLAPSE_V: the two packed gradient slots (y-pass recipe 3)
+  void* vout;       // EPI_COLLAPSE_V: v_max [3][N^3] (R)
+  double vscale;    // EPI_COLLAPSE_V: L / 2 pi
 };
 
 template <typename R, int N, int Q, int EPI>
@@ -536,7 +547,7 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
   // collapse epilogue: the running maximum of this thread's points, fetched with the inputs so
   // that its latency hides behind the transforms
   R fold[R0];
-  if constexpr (EPI == EPI_COLLAPSE) {
+  if constexpr (EPI == EPI_COLLAPSE || EPI == EPI_COLLAPSE_V) {
     const R* F = static_cast<const R*>(args.F);
 #pragma unroll
     for (int s = 0; s < R0; ++s) fold[s] = F[(size_t)(line_ok ? line : Z::LINES - 1) * N + j + s * M0];
@@ -547,20 +558,21 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
   // j = 0, s = R0/2) reads P[N/2], which is never written, and is replaced by zero.
   static_assert(R0 % 2 == 0 && M0 * (R0 / 2) == HZ, "z pass: the first half of the elements is n < N/2");
   const int lineL = line_ok ? line : Z::LINES - 1;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const V* src = in + (size_t)q * PSLOT + (size_t)lineL * N;
+  auto load_line = [&](const V* slot, V(&dst)[R0]) {
+    const V* src = slot + (size_t)lineL * N;
     const V* lo = src + j;
     const V* hi = src + (3 * HZ - j);
 #pragma unroll
-    for (int s = 0; s < R0 / 2; ++s) v[q][s] = lo[s * M0];
+    for (int s = 0; s < R0 / 2; ++s) dst[s] = lo[s * M0];
     {
       const V x = src[j == 0 ? HZ : N - j];
-      v[q][R0 / 2] = j == 0 ? V{R(0), R(0)} : x;
+      dst[R0 / 2] = j == 0 ? V{R(0), R(0)} : x;
     }
 #pragma unroll
-    for (int s = R0 / 2 + 1; s < R0; ++s) v[q][s] = hi[-s * M0];
-  }
+    for (int s = R0 / 2 + 1; s < R0; ++s) dst[s] = hi[-s * M0];
+  };
+#pragma unroll
+  for (int q = 0; q < Q; ++q) load_line(in + (size_t)q * PSLOT, v[q]);
   if constexpr (Z::ZT::QL == Q) {
     E::run(v, lds, s_tw, t);
   } else {
@@ -577,23 +589,45 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
       return c == 0 ? v[0][s].x : c == 1 ? v[0][s].y : v[1][s].x;
     }
   };
-  if constexpr (EPI == EPI_COLLAPSE) {
+  if constexpr (EPI == EPI_COLLAPSE || EPI == EPI_COLLAPSE_V) {
     static_assert(Q == 3, "collapse needs the six components");
     R* F = static_cast<R*>(args.F);
-    if (line_ok) {
+    bool upd[R0];
+#pragma unroll
+    for (int s = 0; s < R0; ++s) {
+      const size_t idx = (size_t)line * N + j + s * M0;
+      R fr;
+      if constexpr (sizeof(R) == 4) {
+        fr = collapse_point_mixed(comp(0, s), comp(1, s), comp(2, s), comp(3, s), comp(4, s), comp(5, s),
+                                  (float)args.cc.sphere_gain);
+      } else {
+        fr = (R)collapse_point(comp(0, s), comp(1, s), comp(2, s), comp(3, s), comp(4, s), comp(5, s), args.cc);
+      }
+      upd[s] = line_ok && fr > fold[s];
+      if (upd[s]) {
+        F[idx] = fr;
+        args.ridx[idx] = (uint8_t)args.r;
+      }
+    }
+    if constexpr (EPI == EPI_COLLAPSE_V) {
+      // v_max: the smoothed gradient at this radius, transformed only now (the Hessian data is
+      // dead) and stored where F_max grew
+      const V* gin = static_cast<const V*>(args.gin);
+      V g[2][R0];
+      load_line(gin, g[0]);
+      load_line(gin + PSLOT, g[1]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) E::run(*reinterpret_cast<V(*)[1][R0]>(&g[q]), lds, s_tw, t);
+      R* vout = static_cast<R*>(args.vout);
+      constexpr size_t VOL = (size_t)N * N * N;
+      const R vs = (R)args.vscale;
 #pragma unroll
       for (int s = 0; s < R0; ++s) {
-        const size_t idx = (size_t)line * N + j + s * M0;
-        R fr;
-        if constexpr (sizeof(R) == 4) {
-          fr = collapse_point_mixed(comp(0, s), comp(1, s), comp(2, s), comp(3, s), comp(4, s), comp(5, s),
-                                    (float)args.cc.sphere_gain);
-        } else {
-          fr = (R)collapse_point(comp(0, s), comp(1, s), comp(2, s), comp(3, s), comp(4, s), comp(5, s), args.cc);
-        }
-        if (fr > fold[s]) {
-          F[idx] = fr;
-          args.ridx[idx] = (uint8_t)args.r;
+        if (upd[s]) {
+          const size_t idx = (size_t)line * N + j + s * M0;
+          vout[idx] = g[0][s].x * vs;
+          vout[VOL + idx] = g[0][s].y * vs;
+          vout[2 * VOL + idx] = g[1][s].x * vs;
         }
       }
     }
@@ -679,6 +713,12 @@ __global__ void k_reset(R* __restrict__ F, uint8_t* __restrict__ ridx, size_t co
     F[i] = R(0);
     ridx[i] = 255;
   }
+}
+
+template <typename R>
+__global__ void k_zero(R* __restrict__ p, size_t count) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = R(0);
 }
 
 }  // namespace pin

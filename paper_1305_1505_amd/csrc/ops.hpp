@@ -25,17 +25,23 @@ struct SizeOps {
   // fused forward-x / inverse-x (2LPT): one input slot -> two output slots
   void (*xpass_fwdinv)(const void* in, void* out, const void* tw, double scale, hipStream_t s);
   // y pass: recipe 0 Hessian (3 half slots -> 3 packed slots), 1 gradient (2 half -> 2 packed),
-  // 2 forward (1 half -> 1 half)
+  // 2 forward (1 half -> 1 half), 3 gradient times i from the Hessian x pass (2 half -> 2 packed)
   void (*ypass)(int recipe, const void* in, void* out, const void* tw, hipStream_t s);
   // z pass (packed slots in) with the collapse epilogue at radius index r
   void (*zpass_collapse)(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain,
                          hipStream_t s);
+  // z pass with the collapse epilogue and v_max: Hessian packed slots `in`, gradient packed
+  // slots `gin`; v_max [3][N^3] written where F_max grows, times vscale
+  void (*zpass_collapse_v)(const void* in, const void* gin, const void* tw, void* F, uint8_t* ridx, void* vmax,
+                           int r, double sphere_gain, double vscale, hipStream_t s);
   // z pass storing nc = 6 (Hessian) or 3 (gradient) real components to out[nc][N^3]
   void (*zpass_store)(int nc, const void* in, const void* tw, void* out, hipStream_t s);
   // z pass computing the 2LPT source and its forward transform along z into one slot
   void (*zpass_mu2)(const void* in, const void* tw, void* out_slot, hipStream_t s);
   void (*grf)(void* dk, uint64_t seed, double norm, double kf, double gamma, double ns, hipStream_t s);
   void (*reset)(void* F, uint8_t* ridx, hipStream_t s);
+  // count reals of the plan's precision set to zero
+  void (*zero)(void* p, size_t count, hipStream_t s);
   // per-point collapse model on [6][count] tensors
   void (*collapse_points)(const void* t6, size_t count, void* F, double sphere_gain, hipStream_t s);
   // launch shapes, for reports

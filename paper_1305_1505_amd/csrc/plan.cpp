@@ -35,7 +35,8 @@ void prep_hessian_input(pin_plan p, const void* dk, hipStream_t s) {
 const char* const kClassNames[KC_COUNT] = {
     "grf",           "reset",          "xpass_hessian", "ypass_hessian", "zpass_collapse",
     "zpass_store",   "xpass_gradient", "ypass_gradient", "zpass_mu2",    "ypass_forward",
-    "xpass_fwdinv",  "collapse_points", "prep"};
+    "xpass_fwdinv",  "collapse_points", "prep",          "ypass_velocity", "zpass_collapse_v",
+    "zero"};
 
 void fail(pin_status s, const std::string& m) { throw PinError(s, m); }
 
@@ -145,6 +146,7 @@ void plan_free(pin_plan p) {
   if (p->X) (void)hipFree(p->X);
   if (p->Y) (void)hipFree(p->Y);
   if (p->G) (void)hipFree(p->G);
+  if (p->V) (void)hipFree(p->V);
   delete p;
 }
 
@@ -179,6 +181,31 @@ void plan_run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, 
     p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
     p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
     p->launch(KC_ZPASS_COLLAPSE, s, [&] { p->ops->zpass_collapse(p->Y, p->tw, F, ridx, r, p->sphere_gain, s); });
+  }
+}
+
+size_t velocity_workspace_bytes(int n, bool fp64) {
+  const size_t rb = fp64 ? 8 : 4;
+  return 4 * (size_t)n * n * (n / 2) * 2 * rb;
+}
+
+void plan_reset_v(pin_plan p, void* F, uint8_t* ridx, void* vmax, hipStream_t s) {
+  plan_reset(p, F, ridx, s);
+  p->launch(KC_ZERO, s, [&] { p->ops->zero(vmax, 3 * (size_t)p->n * p->n * p->n, s); });
+}
+
+void plan_run_radii_v(pin_plan p, const void* dk, void* F, uint8_t* ridx, void* vmax, int r0, int r1, hipStream_t s) {
+  if (p->V == nullptr) p->V = device_alloc(velocity_workspace_bytes(p->n, p->fp64), "workspace V");
+  const double vscale = p->box / (2.0 * 3.14159265358979323846);
+  prep_hessian_input(p, dk, s);
+  for (int r = r0; r < r1; ++r) {
+    const void* w = p->window_row(r);
+    p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
+    p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
+    p->launch(KC_YPASS_VEL, s, [&] { p->ops->ypass(3, p->X, p->V, p->tw, s); });
+    p->launch(KC_ZPASS_COLLAPSE_V, s, [&] {
+      p->ops->zpass_collapse_v(p->Y, p->V, p->tw, F, ridx, vmax, r, p->sphere_gain, vscale, s);
+    });
   }
 }
 

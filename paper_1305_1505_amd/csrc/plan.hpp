@@ -54,6 +54,9 @@ enum KernelClass {
   KC_XPASS_FWDINV,
   KC_COLLAPSE_POINTS,
   KC_PREP,
+  KC_YPASS_VEL,
+  KC_ZPASS_COLLAPSE_V,
+  KC_ZERO,
   KC_COUNT
 };
 extern const char* const kClassNames[KC_COUNT];
@@ -82,6 +85,7 @@ struct pin_plan_s {
   void* X = nullptr;      // 4 half slots (= 2 packed slots)
   void* Y = nullptr;      // 6 half slots (= 3 packed slots)
   void* G = nullptr;      // 1 half slot: the radius-independent Hessian input
+  void* V = nullptr;      // 4 half slots (= 2 packed slots) for v_max, allocated on first use
   size_t slot_bytes = 0;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[pin::KC_COUNT];
@@ -125,6 +129,10 @@ void plan_generate_field(pin_plan p, uint64_t seed, void* dk, hipStream_t s);
 void plan_reset(pin_plan p, void* F, uint8_t* ridx, hipStream_t s);
 void plan_run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, int r1, hipStream_t s);
 void plan_deformation_tensor(pin_plan p, const void* dk, int r, void* T6, hipStream_t s);
+// v_max variants: the reset also zeroes v_max [3][N^3]; the radii also record v_max
+void plan_reset_v(pin_plan p, void* F, uint8_t* ridx, void* vmax, hipStream_t s);
+void plan_run_radii_v(pin_plan p, const void* dk, void* F, uint8_t* ridx, void* vmax, int r0, int r1, hipStream_t s);
+size_t velocity_workspace_bytes(int n, bool fp64);
 void plan_displacements(pin_plan p, const void* dk, void* psi1, void* psi2, hipStream_t s);
 
 }  // namespace pin
