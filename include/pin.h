@@ -141,6 +141,28 @@ pin_status pin_collapse_times_range_v(pin_plan plan, const void* dk, void* F, ui
 pin_status pin_collapse_times_v(pin_plan plan, const void* dk, void* F, uint8_t* ridx, void* vmax,
                                 hipStream_t stream);
 
+/* Growing-mode clock (section "Collapse times": the linear growing mode D, normalised to 1 at
+ * z = 0, is the time coordinate; F = 1/D at collapse; section "Simulations": flat LambdaCDM).
+ * pin_plan_set_growth tabulates D for a flat LambdaCDM universe without radiation,
+ * D(a) ~ E(a) Int_0^a da'/(a' E(a'))^3 with E^2 = omega_m a^-3 + 1 - omega_m (0 < omega_m <= 1;
+ * 1 is Einstein-de Sitter, D = a), in float64 on the host, and keeps it on the device with the
+ * plan (stream-ordered upload; returns when done).  pin_collapse_redshift writes, for each of
+ * count values F (device, plan precision), the redshift z_c with D(z_c) = 1/F to zc (device, plan
+ * precision); z_c = -1 where F <= 0 or where 1/F is beyond D(a = 1e6) (no collapse).  Computed
+ * in float64 (relative error of 1 + z_c below 1e-12).  PIN_ERR_INVALID_ARG without a table. */
+pin_status pin_plan_set_growth(pin_plan plan, double omega_m, hipStream_t stream);
+pin_status pin_collapse_redshift(pin_plan plan, const void* F, size_t count, void* zc, hipStream_t stream);
+
+/* Smoothing-radius ladder (section "Collapse times": radii chosen so that the mass variances of
+ * the smoothed field are logarithmically spaced by 0.15 dex).  Host only.  sigma^2(R) is the
+ * variance of the field smoothed with the plan's Gaussian window, 1/(2 pi^2) Int k^2 P(k)
+ * exp(-k^2 R^2) dk for the BBKS spectrum (gamma, ns; the amplitude cancels), R = cells * box / n
+ * Mpc/h.  From r_max_cells the ladder descends with sigma^2 growing by 10^dex per step while the
+ * radius stays >= r_min_cells; *count receives its length, radii_cells (host, capacity entries;
+ * may be NULL to query the length) the radii, largest first. */
+pin_status pin_radius_ladder(int n, double box, double r_max_cells, double r_min_cells, double dex, double gamma,
+                             double ns, double* radii_cells, int capacity, int* count);
+
 /* The six deformation-tensor components at radius index r (r = -1: unsmoothed), written to T6
  * (device, [6][N][N][N] real, order xx, xy, xz, yy, yz, zz). */
 pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6,

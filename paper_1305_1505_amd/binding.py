@@ -64,6 +64,11 @@ _sig = {
     "pin_collapse_reset_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pin_collapse_times_range_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "pin_collapse_times_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pin_plan_set_growth": (ctypes.c_int, [_vp, ctypes.c_double, _vp]),
+    "pin_collapse_redshift": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
+    "pin_radius_ladder": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "pin_displacements": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
@@ -155,6 +160,24 @@ def pin_collapse_times_range_v(plan, dk, F, ridx, vmax, r_begin, r_end, stream=0
 
 def pin_collapse_times_v(plan, dk, F, ridx, vmax, stream=0):
     _check(lib.pin_collapse_times_v(plan, _vp(dk), _vp(F), _vp(ridx), _vp(vmax), _vp(stream)))
+
+
+def pin_plan_set_growth(plan, omega_m, stream=0):
+    _check(lib.pin_plan_set_growth(plan, float(omega_m), _vp(stream)))
+
+
+def pin_collapse_redshift(plan, F, count, zc, stream=0):
+    _check(lib.pin_collapse_redshift(plan, _vp(F), ctypes.c_size_t(int(count)), _vp(zc), _vp(stream)))
+
+
+def pin_radius_ladder(n, box, r_max_cells, r_min_cells, dex=0.15, gamma=0.21, ns=1.0):
+    """The radius ladder as a list (host only): first the length, then the radii."""
+    count = ctypes.c_int(0)
+    args = (int(n), float(box), float(r_max_cells), float(r_min_cells), float(dex), float(gamma), float(ns))
+    _check(lib.pin_radius_ladder(*args, None, 0, ctypes.byref(count)))
+    out = (ctypes.c_double * max(count.value, 1))()
+    _check(lib.pin_radius_ladder(*args, out, count.value, ctypes.byref(count)))
+    return [out[i] for i in range(count.value)]
 
 
 def pin_deformation_tensor(plan, dk, r, T6, stream=0):
@@ -277,6 +300,16 @@ class Plan:
         pin_collapse_times_range_v(self.handle, dk.data_ptr(), F.data_ptr(), ridx.data_ptr(), vmax.data_ptr(),
                                    r_begin, r_end, self._stream())
         return F, ridx, vmax
+
+    def set_growth(self, omega_m):
+        pin_plan_set_growth(self.handle, omega_m, self._stream())
+
+    def collapse_redshift(self, F):
+        """z_c for a device tensor of F values (plan precision)."""
+        F = F.contiguous()
+        z = self.torch.empty_like(F)
+        pin_collapse_redshift(self.handle, F.data_ptr(), F.numel(), z.data_ptr(), self._stream())
+        return z
 
     def deformation_tensor(self, dk, r):
         n = self.n

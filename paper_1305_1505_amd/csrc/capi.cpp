@@ -1,7 +1,10 @@
 // C ABI of libpin (include/pin.h): argument validation around the plan operations of plan.cpp.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "pin.h"
+#include "host_math.hpp"
 #include "plan.hpp"
 
 using namespace pin;
@@ -137,6 +140,57 @@ pin_status pin_collapse_times_v(pin_plan plan, const void* dk, void* F, uint8_t*
     check_device_range(vmax, 3 * plan->real_field_bytes(), "vmax");
     plan_reset_v(plan, F, ridx, vmax, stream);
     plan_run_radii_v(plan, dk, F, ridx, vmax, 0, plan->nr, stream);
+  });
+}
+
+pin_status pin_plan_set_growth(pin_plan plan, double omega_m, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (!(omega_m > 0.0 && omega_m <= 1.0)) fail(PIN_ERR_INVALID_ARG, "omega_m must be in (0, 1]");
+    const GrowthTable g = growth_table(omega_m);
+    std::vector<double> host(g.d);
+    host.insert(host.end(), g.dd.begin(), g.dd.end());
+    if (plan->growth == nullptr) plan->growth = device_alloc(host.size() * sizeof(double), "growth table");
+    hip_check(hipMemcpyAsync(plan->growth, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, stream),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    plan->growth_y0 = g.y0;
+    plan->growth_h = g.h;
+    plan->growth_a_per_D = g.a_per_D;
+    plan->growth_lom = g.lambda_over_m;
+  });
+}
+
+pin_status pin_collapse_redshift(pin_plan plan, const void* F, size_t count, void* zc, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (plan->growth == nullptr) fail(PIN_ERR_INVALID_ARG, "no growth table: call pin_plan_set_growth first");
+    if (count == 0) return;
+    if (count > ((size_t)1 << 40)) fail(PIN_ERR_INVALID_ARG, "count is too large");
+    check_device_range(F, count * plan->real_bytes, "F");
+    check_device_range(zc, count * plan->real_bytes, "zc");
+    const double* d = static_cast<const double*>(plan->growth);
+    plan->launch(KC_REDSHIFT, stream, [&] {
+      plan->ops->redshift(F, count, d, d + kGrowthNodes, kGrowthNodes, plan->growth_y0, plan->growth_h,
+                          plan->growth_a_per_D, plan->growth_lom, zc, stream);
+    });
+  });
+}
+
+pin_status pin_radius_ladder(int n, double box, double r_max_cells, double r_min_cells, double dex, double gamma,
+                             double ns, double* radii_cells, int capacity, int* count) {
+  return guarded([&] {
+    if (n < 2 || !(box > 0.0)) fail(PIN_ERR_INVALID_ARG, "n must be >= 2 and box > 0");
+    if (!(r_max_cells > r_min_cells && r_min_cells > 0.0)) fail(PIN_ERR_INVALID_ARG, "need r_max > r_min > 0");
+    if (!(dex > 0.0)) fail(PIN_ERR_INVALID_ARG, "dex must be > 0");
+    if (!(gamma > 0.0)) fail(PIN_ERR_INVALID_ARG, "gamma must be > 0");
+    if (count == nullptr) fail(PIN_ERR_INVALID_ARG, "count is NULL");
+    const std::vector<double> r = radius_ladder(n, box, r_max_cells, r_min_cells, dex, gamma, ns);
+    *count = (int)r.size();
+    if (radii_cells != nullptr) {
+      if (capacity < (int)r.size()) fail(PIN_ERR_INVALID_ARG, "capacity is smaller than the ladder (see *count)");
+      for (size_t i = 0; i < r.size(); ++i) radii_cells[i] = r[i];
+    }
   });
 }
 

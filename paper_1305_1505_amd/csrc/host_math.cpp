@@ -79,6 +79,119 @@ double sigma2_tophat_unit(double radius, double gamma, double ns) {
   return total / (2.0 * kPi * kPi);
 }
 
+double sigma2_gaussian_unit(double radius, double gamma, double ns) {
+  static const GaussLegendre gl;
+  const double a = std::log(1e-7), b = std::log(40.0 / radius);
+  const int panels = 2000;
+  const double h = (b - a) / panels;
+  double total = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double mid = a + (p + 0.5) * h;
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) {
+      const double k = std::exp(mid + 0.5 * h * gl.x[i]);
+      const double t = bbks_transfer(k, gamma);
+      s += gl.w[i] * k * k * k * std::pow(k, ns) * t * t * std::exp(-(k * radius) * (k * radius));
+    }
+    total += 0.5 * h * s;
+  }
+  return total / (2.0 * kPi * kPi);
+}
+
+std::vector<double> radius_ladder(int n, double box, double r_max, double r_min, double dex, double gamma,
+                                  double ns) {
+  const double cell = box / n;
+  auto lns2 = [&](double lr) { return std::log(sigma2_gaussian_unit(std::exp(lr) * cell, gamma, ns)); };
+  std::vector<double> radii{r_max};
+  double cur = lns2(std::log(r_max));
+  const double step = dex * std::log(10.0);
+  while (true) {
+    const double target = cur + step;
+    // sigma^2 grows as R shrinks: bracket [lo, hi] in ln R with lns2(lo) >= target > lns2(hi)
+    double hi = std::log(radii.back()), lo = hi;
+    double flo = cur - target;
+    while (flo < 0.0) {
+      hi = lo;
+      lo -= 0.5;
+      if (std::exp(lo) < 1e-3 * r_min) return radii;
+      flo = lns2(lo) - target;
+    }
+    double fhi = lns2(hi) - target;
+    // Illinois regula falsi on ln R
+    double x = lo;
+    for (int it = 0; it < 200 && hi - lo > 1e-14; ++it) {
+      x = (lo * fhi - hi * flo) / (fhi - flo);
+      const double fx = lns2(x) - target;
+      if ((fx >= 0.0) == (flo >= 0.0)) {
+        lo = x;
+        flo = fx;
+        fhi *= 0.5;
+      } else {
+        hi = x;
+        fhi = fx;
+        flo *= 0.5;
+      }
+      if (fx == 0.0) break;
+    }
+    const double r = std::exp(x);
+    if (r < r_min) return radii;
+    radii.push_back(r);
+    cur = target;
+  }
+}
+
+GrowthTable growth_table(double om) {
+  static const GaussLegendre gl;
+  const double ol = 1.0 - om;
+  GrowthTable g;
+  g.y0 = std::log(1e-3);
+  g.h = (std::log(1e6) - g.y0) / (kGrowthNodes - 1);
+  g.lambda_over_m = ol / om;
+  // I(a) = Int_0^a da' / (a' E)^3 = Int x^(3/2) (om + ol x^3)^(-3/2) dx; in y = ln x the
+  // integrand is x^(5/2) (om + ol x^3)^(-3/2)
+  auto f = [&](double y) {
+    const double x = std::exp(y);
+    return std::pow(x, 2.5) * std::pow(om + ol * x * x * x, -1.5);
+  };
+  auto panel = [&](double y_a, double y_b) {
+    double s = 0.0;
+    const double mid = 0.5 * (y_a + y_b), half = 0.5 * (y_b - y_a);
+    for (int i = 0; i < 16; ++i) s += gl.w[i] * f(mid + half * gl.x[i]);
+    return half * s;
+  };
+  const double ys = std::log(1e-8);
+  double I = 0.4 * std::pow(1e-8, 2.5) * std::pow(om, -1.5);   // leading term below a = 1e-8
+  // up to the first node, then node by node (four panels per interval)
+  const int pre = 4000;
+  for (int p = 0; p < pre; ++p) I += panel(ys + (g.y0 - ys) * p / pre, ys + (g.y0 - ys) * (p + 1) / pre);
+  auto d_unnorm = [&](double a, double Ia) { return 2.5 * om * std::sqrt(om / (a * a * a) + ol) * Ia; };
+  auto dd_unnorm = [&](double a, double Ia) {   // a dD/da
+    const double e = std::sqrt(om / (a * a * a) + ol);
+    return 2.5 * om * (-1.5 * om / (a * a * a) / e * Ia + e * a * std::pow(a, 1.5) * std::pow(om + ol * a * a * a, -1.5));
+  };
+  std::vector<double> Iy(kGrowthNodes);
+  Iy[0] = I;
+  for (int i = 1; i < kGrowthNodes; ++i) {
+    const double ya = g.y0 + (i - 1) * g.h;
+    for (int q = 0; q < 4; ++q) I += panel(ya + g.h * q / 4, ya + g.h * (q + 1) / 4);
+    Iy[i] = I;
+  }
+  // normalisation at a = 1 (y = 0)
+  double I1 = Iy[0];
+  const int p1 = 4000;
+  for (int p = 0; p < p1; ++p) I1 += panel(g.y0 * (1.0 - (double)p / p1), g.y0 * (1.0 - (double)(p + 1) / p1));
+  const double norm = d_unnorm(1.0, I1);
+  g.a_per_D = norm;
+  g.d.resize(kGrowthNodes);
+  g.dd.resize(kGrowthNodes);
+  for (int i = 0; i < kGrowthNodes; ++i) {
+    const double a = std::exp(g.y0 + i * g.h);
+    g.d[i] = d_unnorm(a, Iy[i]) / norm;
+    g.dd[i] = dd_unnorm(a, Iy[i]) / norm;
+  }
+  return g;
+}
+
 double amplitude_for_sigma8(double sigma8, double gamma, double ns) {
   return sigma8 * sigma8 / sigma2_tophat_unit(8.0, gamma, ns);
 }

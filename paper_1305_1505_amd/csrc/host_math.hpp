@@ -12,6 +12,21 @@ double tophat_window(double x);
 // sigma^2(R) = 1/(2 pi^2) Int k^2 P(k) W_TH(kR)^2 dk for P = k^ns T^2 (unit amplitude), by
 // composite 16-point Gauss-Legendre quadrature in ln k over [1e-7, 1e3] h/Mpc.
 double sigma2_tophat_unit(double radius, double gamma, double ns);
+// sigma^2(R) with the Gaussian window, 1/(2 pi^2) Int k^2 P(k) exp(-k^2 R^2) dk (unit amplitude).
+double sigma2_gaussian_unit(double radius, double gamma, double ns);
+// Radii in cells, largest first from r_max, each with sigma^2 10^dex times the previous one's
+// (Gaussian window, box/n Mpc/h per cell), while >= r_min.
+std::vector<double> radius_ladder(int n, double box, double r_max, double r_min, double dex, double gamma,
+                                  double ns);
+// Growing mode of flat LambdaCDM (no radiation), normalised to D(a = 1) = 1, tabulated on
+// y = ln a at kGrowthNodes nodes from ln 1e-3 to ln 1e6: D and dD/dy at each node, and
+// a_per_D = lim_{a->0} a / D (= the unnormalised D at a = 1).
+constexpr int kGrowthNodes = 8192;
+struct GrowthTable {
+  double y0 = 0, h = 0, a_per_D = 0, lambda_over_m = 0;
+  std::vector<double> d, dd;
+};
+GrowthTable growth_table(double omega_m);
 // Amplitude A with sigma^2(8 Mpc/h) = sigma8^2.
 double amplitude_for_sigma8(double sigma8, double gamma, double ns);
 // Root of the 3rd-order EdS sphere series 1 - x/3 - x^2/21 - 23 x^3/1701 (bisection), and the

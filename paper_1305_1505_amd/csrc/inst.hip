@@ -128,6 +128,16 @@ void reset(void* F, uint8_t* ridx, hipStream_t s) {
   hipLaunchKernelGGL((k_reset<RR>), dim3(grid), dim3(block), 0, s, static_cast<RR*>(F), ridx, total);
 }
 
+void redshift(const void* F, size_t count, const double* d, const double* dd, int m, double y0, double h,
+              double a_per_D, double lambda_over_m, void* z, hipStream_t s) {
+  if (count == 0) return;
+  GrowthArgs g{d, dd, m, y0, h, a_per_D, lambda_over_m};
+  const int block = 256;
+  const int grid = (int)((count + block - 1) / block);
+  hipLaunchKernelGGL((k_redshift<RR>), dim3(grid), dim3(block), 0, s, static_cast<const RR*>(F), count, g,
+                     static_cast<RR*>(z));
+}
+
 void zero(void* p, size_t count, hipStream_t s) {
   if (count == 0) return;
   const int block = 256;
@@ -152,7 +162,7 @@ void collapse_points(const void* t6, size_t count, void* F, double sphere_gain, 
 const SizeOps* PIN_CAT(ops_, PIN_INST_FP64, PIN_INST_N)() {
   static const SizeOps ops = {
       NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, ypass, zpass_collapse, zpass_collapse_v, zpass_store,
-      zpass_mu2, grf, reset, zero, collapse_points,
+      zpass_mu2, grf, reset, redshift, zero, collapse_points,
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{ZPass<RR, NN, 3, EPI_COLLAPSE>::GRID, ZPass<RR, NN, 3, EPI_COLLAPSE>::T}};

@@ -715,6 +715,52 @@ __global__ void k_reset(R* __restrict__ F, uint8_t* __restrict__ ridx, size_t co
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Collapse redshift: z_c with D(z_c) = 1/F, D the growing mode normalised to 1 at z = 0,
+// tabulated (float64) on y = ln a at m nodes y0 + i h with D and dD/dy.  The interval holding
+// 1/F is found by bisection on the monotone D, then y by Newton steps on the cubic Hermite
+// interpolant of D(y) there.  Below the first node D = a (1 - (2/11)(Lambda/Om) a^3 + ...) / a_per_D
+// is inverted directly; F <= 0, or 1/F beyond the last node (a > 1e6), gives z_c = -1.
+struct GrowthArgs {
+  const double* d;
+  const double* dd;
+  int m;
+  double y0, h, a_per_D, lambda_over_m;
+};
+
+template <typename R>
+__global__ void k_redshift(const R* __restrict__ F, size_t count, GrowthArgs g, R* __restrict__ z) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double f = (double)F[i];
+  double out = -1.0;
+  if (f > 0.0) {
+    const double t = 1.0 / f;
+    if (t < g.d[0]) {
+      const double a0 = t * g.a_per_D;
+      const double a = a0 * (1.0 + (2.0 / 11.0) * g.lambda_over_m * a0 * a0 * a0);
+      out = 1.0 / a - 1.0;
+    } else if (t < g.d[g.m - 1]) {
+      int lo = 0, hi = g.m - 1;   // d[lo] <= t < d[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.d[mid] <= t) lo = mid; else hi = mid;
+      }
+      const double d0 = g.d[lo], d1 = g.d[hi], m0 = g.dd[lo] * g.h, m1 = g.dd[hi] * g.h;
+      double s = (t - d0) / (d1 - d0);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const double s2 = s * s, s3 = s2 * s;
+        const double hv = (2 * s3 - 3 * s2 + 1) * d0 + (s3 - 2 * s2 + s) * m0 + (-2 * s3 + 3 * s2) * d1 + (s3 - s2) * m1;
+        const double hp = (6 * s2 - 6 * s) * d0 + (3 * s2 - 4 * s + 1) * m0 + (-6 * s2 + 6 * s) * d1 + (3 * s2 - 2 * s) * m1;
+        s = fmin(1.0, fmax(0.0, s - (hv - t) / hp));
+      }
+      out = exp(-(g.y0 + (lo + s) * g.h)) - 1.0;
+    }
+  }
+  z[i] = (R)out;
+}
+
 template <typename R>
 __global__ void k_zero(R* __restrict__ p, size_t count) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

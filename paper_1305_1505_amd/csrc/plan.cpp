@@ -36,7 +36,7 @@ const char* const kClassNames[KC_COUNT] = {
     "grf",           "reset",          "xpass_hessian", "ypass_hessian", "zpass_collapse",
     "zpass_store",   "xpass_gradient", "ypass_gradient", "zpass_mu2",    "ypass_forward",
     "xpass_fwdinv",  "collapse_points", "prep",          "ypass_velocity", "zpass_collapse_v",
-    "zero"};
+    "zero",          "redshift"};
 
 void fail(pin_status s, const std::string& m) { throw PinError(s, m); }
 
@@ -147,6 +147,7 @@ void plan_free(pin_plan p) {
   if (p->Y) (void)hipFree(p->Y);
   if (p->G) (void)hipFree(p->G);
   if (p->V) (void)hipFree(p->V);
+  if (p->growth) (void)hipFree(p->growth);
   delete p;
 }
 

@@ -57,6 +57,7 @@ enum KernelClass {
   KC_YPASS_VEL,
   KC_ZPASS_COLLAPSE_V,
   KC_ZERO,
+  KC_REDSHIFT,
   KC_COUNT
 };
 extern const char* const kClassNames[KC_COUNT];
@@ -86,6 +87,8 @@ struct pin_plan_s {
   void* Y = nullptr;      // 6 half slots (= 3 packed slots)
   void* G = nullptr;      // 1 half slot: the radius-independent Hessian input
   void* V = nullptr;      // 4 half slots (= 2 packed slots) for v_max, allocated on first use
+  void* growth = nullptr; // growth table (D then dD/dy, float64) after pin_plan_set_growth
+  double growth_y0 = 0, growth_h = 0, growth_a_per_D = 0, growth_lom = 0;
   size_t slot_bytes = 0;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[pin::KC_COUNT];
