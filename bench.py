@@ -300,6 +300,12 @@ def main():
     collapse_v()
     vel_ms = timed(collapse_v)
     del vmax
+    # collapse redshift of every point (flat LambdaCDM, Omega_m 0.25): 2 x real bytes per point
+    zc = torch.empty_like(F)
+    B.pin_plan_set_growth(plan.handle, 0.25, stream)
+    B.pin_collapse_redshift(plan.handle, F.data_ptr(), n ** 3, zc.data_ptr(), stream)
+    z_ms = timed(lambda: B.pin_collapse_redshift(plan.handle, F.data_ptr(), n ** 3, zc.data_ptr(), stream))
+    del zc
     disp_ms = timed(lambda: B.pin_displacements(plan.handle, dk.data_ptr(), p1.data_ptr(), p2.data_ptr(), stream))
     # whole-path roofline at the collapse-only rate: algorithmic bytes per grid-point x radius
     # update of these passes (19 workspace slots of 4 B per point plus F read/write and the
@@ -370,6 +376,7 @@ def main():
                    "n": n, "box_mpc_h": box, "n_radii": len(radii), "precision": cfg["prec"]},
         "collapse_only": {"updates_per_s": rate, "ms": round(collapse_ms, 2), "runs_ms": [round(x, 2) for x in runs]},
         "collapse_with_velocity": {"updates_per_s": updates / (vel_ms * 1e-3), "ms": round(vel_ms, 2)},
+        "collapse_redshift": {"ms": round(z_ms, 3), "GB/s": round(2 * real_bytes * n ** 3 / (z_ms * 1e-3) / 1e9, 1)},
         "field_ms": round(field_ms, 3),
         "displacements_ms": round(disp_ms, 3),
         "path_roofline": path_roofline,

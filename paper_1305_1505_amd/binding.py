@@ -13,6 +13,11 @@ device and calls the same entry points.
 import ctypes
 import os
 
+# torch's ROCm build carries its own HIP runtime (libamdhip64), which libpin.so also links: load
+# torch first so that the process holds one runtime.  Loading libpin first brings in the system
+# runtime, and torch's own then finds no GPU.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpin.so")
 if not os.path.exists(LIB_PATH):
