@@ -55,7 +55,7 @@ def measured_traffic(cls, n, prec):
             "write_bytes": k["write_bytes"], "source": "profiles/traffic_c512_fp32.json"}
 
 
-def cpu_baseline(sample_n=64, radius_stride=4):
+def cpu_baseline(sample_n=64, radius_stride=1):
     """The FP64 oracle on a bounded sample of the workload: a sample_n^3 grid with the same cell
     size (box scaled), every radius_stride-th radius, full step (field, collapse, displacements)."""
     import numpy as np

@@ -16,6 +16,11 @@ What it computes, in the paper's order (section "Collapse times"):
                      used is stated in that module's header.
 * ``run``         -- F_max and R_max over all radii (the trajectory maximum), and the closing
                      Zel'dovich and 2LPT displacement fields.
+* ``lpt3``        -- the third-order displacement named in the conclusions, read as standard EdS
+                     3LPT (longitudinal and transverse parts), pinned by the equations of motion.
+* ``points``      -- deformation tensor, collapse times and displacements at single grid points
+                     by direct summation, for grids too large for the full-grid functions.
+* ``growth``      -- the growing mode D(z) of flat LambdaCDM and the sigma^2 radius ladder.
 * ``dft``         -- naive O(N^6) discrete Fourier transforms used to pin the library FFT.
 * ``philox``      -- the Philox4x32-10 counter-based generator, written from its published
                      definition (Salmon, Moraes, Dror & Shaw, SC'11).
@@ -23,4 +28,4 @@ What it computes, in the paper's order (section "Collapse times"):
 Everything is float64 NumPy/SciPy on CPU cores.
 """
 
-from . import philox, spectrum, field, hessian, collapse, run, dft, metrics  # noqa: F401
+from . import philox, spectrum, field, hessian, collapse, run, dft, metrics, lpt3  # noqa: F401
