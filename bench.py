@@ -307,6 +307,11 @@ def main():
     z_ms = timed(lambda: B.pin_collapse_redshift(plan.handle, F.data_ptr(), n ** 3, zc.data_ptr(), stream))
     del zc
     disp_ms = timed(lambda: B.pin_displacements(plan.handle, dk.data_ptr(), p1.data_ptr(), p2.data_ptr(), stream))
+    # third-order displacement, after one warm-up call (which allocates its workspace)
+    p3 = torch.empty((3, n, n, n), dtype=plan.real, device="cuda")
+    B.pin_lpt3_displacement(plan.handle, dk.data_ptr(), p3.data_ptr(), stream)
+    lpt3_ms = timed(lambda: B.pin_lpt3_displacement(plan.handle, dk.data_ptr(), p3.data_ptr(), stream))
+    del p3
     # whole-path roofline at the collapse-only rate: algorithmic bytes per grid-point x radius
     # update of these passes (19 workspace slots of 4 B per point plus F read/write and the
     # index) and the floor of any out-of-core 3D FFT design (spectrum once, one 3-component
@@ -379,6 +384,7 @@ def main():
         "collapse_redshift": {"ms": round(z_ms, 3), "GB/s": round(2 * real_bytes * n ** 3 / (z_ms * 1e-3) / 1e9, 1)},
         "field_ms": round(field_ms, 3),
         "displacements_ms": round(disp_ms, 3),
+        "lpt3_ms": round(lpt3_ms, 3),
         "path_roofline": path_roofline,
         "fp64": fp64,
         "roofline": roofline,

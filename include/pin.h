@@ -175,6 +175,19 @@ pin_status pin_deformation_tensor(pin_plan plan, const void* dk, int r, void* T6
 pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* psi2,
                              hipStream_t stream);
 
+/* Third-order displacement at D = 1 in Mpc/h (conclusions: halo positions from 3rd-order LPT;
+ * the terms are those of standard Einstein-de Sitter 3LPT, x = q + D psi1 + D^2 psi2 + D^3 psi3),
+ * psi3 [3][N][N][N] real (device, plan precision, caller-owned; components x, y, z):
+ *     div psi3 = det(T1)/3 - (10/21) ((tr T1)(tr T2) - tr(T1 T2))/2,  curl psi3 = C/7,
+ *     C_i = eps_ijk (T1 T2)_jk,
+ * T1 the unsmoothed tensor of pin_displacements, T2 the Hessian of phi2 with lap phi2 = mu2(T1);
+ * i.e. psi3(k) = i (-k S(k) + k x c(k)) / k^2 with S and c the forward transforms of the
+ * divergence and of C/7 (k = 0 and Nyquist modes zeroed in every spectrum, no dealiasing).  The first call on a plan allocates
+ * pin_plan_lpt3_workspace_bytes of device memory more, kept until pin_plan_destroy;
+ * PIN_ERR_OUT_OF_MEMORY if that fails.  dk is the half spectrum (device). */
+pin_status pin_plan_lpt3_workspace_bytes(const pin_plan_desc* desc, size_t* bytes);
+pin_status pin_lpt3_displacement(pin_plan plan, const void* dk, void* psi3, hipStream_t stream);
+
 /* eq. F per point: the inverse collapse time of the ellipsoidal collapse model (the per-point
  * step of pin_collapse_times) for caller-given tensors.  T6 (device, [6][count] of the plan's
  * real type, components xx, xy, xz, yy, yz, zz) -> F (device, [count]).  Model: lambda_1 = the

@@ -75,6 +75,8 @@ _sig = {
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "pin_displacements": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pin_plan_lpt3_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "pin_lpt3_displacement": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
     "pin_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -191,6 +193,16 @@ def pin_deformation_tensor(plan, dk, r, T6, stream=0):
 
 def pin_displacements(plan, dk, psi1, psi2, stream=0):
     _check(lib.pin_displacements(plan, _vp(dk), _vp(psi1 or None), _vp(psi2 or None), _vp(stream)))
+
+
+def pin_plan_lpt3_workspace_bytes(desc):
+    out = ctypes.c_size_t()
+    _check(lib.pin_plan_lpt3_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def pin_lpt3_displacement(plan, dk, psi3, stream=0):
+    _check(lib.pin_lpt3_displacement(plan, _vp(dk), _vp(psi3), _vp(stream)))
 
 
 def pin_inverse_collapse_time(plan, T6, count, F, stream=0):
@@ -339,6 +351,14 @@ class Plan:
         pin_displacements(self.handle, dk.data_ptr(), p1.data_ptr() if p1 is not None else 0,
                           p2.data_ptr() if p2 is not None else 0, self._stream())
         return p1, p2
+
+    def lpt3_displacement(self, dk):
+        """psi3 (3, N, N, N) at D = 1 in Mpc/h (pin_lpt3_displacement)."""
+        n = self.n
+        dk = self._as_spectrum(dk)
+        p3 = self.torch.empty((3, n, n, n), dtype=self.real, device="cuda")
+        pin_lpt3_displacement(self.handle, dk.data_ptr(), p3.data_ptr(), self._stream())
+        return p3
 
 
 # ---------------------------------------------------------------------------------------------

@@ -215,6 +215,23 @@ pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* ps
   });
 }
 
+pin_status pin_plan_lpt3_workspace_bytes(const pin_plan_desc* desc, size_t* bytes) {
+  return guarded([&] {
+    validate_desc(desc);
+    if (bytes == nullptr) fail(PIN_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = lpt3_workspace_bytes(desc->n, desc->prec == PIN_FP64);
+  });
+}
+
+pin_status pin_lpt3_displacement(pin_plan plan, const void* dk, void* psi3, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    check_device_range(dk, plan->half_spectrum_bytes(), "dk");
+    check_device_range(psi3, 3 * plan->real_field_bytes(), "psi3");
+    plan_lpt3_displacement(plan, dk, psi3, stream);
+  });
+}
+
 pin_status pin_inverse_collapse_time(pin_plan plan, const void* T6, size_t count, void* F, hipStream_t stream) {
   return guarded([&] {
     check_plan(plan);

@@ -38,9 +38,20 @@ void xpass(int mode, const void* dk, void* out, const void* wtab, const void* tw
   }
 }
 
-void xpass_fwdinv(const void* in, void* out, const void* tw, double scale, hipStream_t s) {
+void xpass_fwdinv(bool hess, const void* in, void* out, const void* tw, double scale, hipStream_t s) {
   using S = Strided<RR, NN, +1>;
-  hipLaunchKernelGGL((k_xpass_fwdinv<RR, NN>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+  if (hess) {
+    hipLaunchKernelGGL((k_xpass_fwdinv<RR, NN, true>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw), (RR)scale);
+  } else {
+    hipLaunchKernelGGL((k_xpass_fwdinv<RR, NN, false>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw), (RR)scale);
+  }
+}
+
+void xpass_lpt3(const void* in, void* out, const void* tw, double scale, hipStream_t s) {
+  using S = Strided<RR, NN, +1>;
+  hipLaunchKernelGGL((k_xpass_lpt3<RR, NN>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
                      static_cast<VV*>(out), static_cast<const VV*>(tw), (RR)scale);
 }
 
@@ -56,6 +67,10 @@ void ypass(int recipe, const void* in, void* out, const void* tw, hipStream_t s)
   } else if (recipe == 3) {
     using S = Strided<RR, NN, +1>;
     hipLaunchKernelGGL((k_ypass_packed<RR, NN, 3>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+  } else if (recipe == 4) {
+    using S = Strided<RR, NN, +1>;
+    hipLaunchKernelGGL((k_ypass_packed<RR, NN, 4>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
                        static_cast<VV*>(out), static_cast<const VV*>(tw));
   } else {
     using S = Strided<RR, NN, -1>;
@@ -105,11 +120,21 @@ void zpass_store(int nc, const void* in, const void* tw, void* out, hipStream_t 
   }
 }
 
-void zpass_mu2(const void* in, const void* tw, void* out_slot, hipStream_t s) {
+void zpass_mu2(const void* in, const void* tw, void* out_slot, void* t6, hipStream_t s) {
   using Z = ZPass<RR, NN, 3, EPI_MU2>;
   ZArgs a{};
   a.out = out_slot;
+  a.t6 = t6;
   hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_MU2>), dim3(Z::GRID), dim3(Z::T), 0, s,
+                     static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
+}
+
+void zpass_lpt3(const void* in, const void* t1, const void* tw, void* out_slots, hipStream_t s) {
+  using Z = ZPass<RR, NN, 3, EPI_LPT3>;
+  ZArgs a{};
+  a.out = out_slots;
+  a.t6 = const_cast<void*>(t1);
+  hipLaunchKernelGGL((k_zpass<RR, NN, 3, EPI_LPT3>), dim3(Z::GRID), dim3(Z::T), 0, s,
                      static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
 }
 
@@ -161,8 +186,8 @@ void collapse_points(const void* t6, size_t count, void* F, double sphere_gain, 
 
 const SizeOps* PIN_CAT(ops_, PIN_INST_FP64, PIN_INST_N)() {
   static const SizeOps ops = {
-      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, ypass, zpass_collapse, zpass_collapse_v, zpass_store,
-      zpass_mu2, grf, reset, redshift, zero, collapse_points,
+      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, xpass_lpt3, ypass, zpass_collapse, zpass_collapse_v,
+      zpass_store, zpass_mu2, zpass_lpt3, grf, reset, redshift, zero, collapse_points,
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{ZPass<RR, NN, 3, EPI_COLLAPSE>::GRID, ZPass<RR, NN, 3, EPI_COLLAPSE>::T}};

@@ -264,10 +264,13 @@ k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fused forward-x / inverse-x pass of the 2LPT displacement: reads the (z-forward, y-forward)
-// transformed source from a half slot, completes the forward transform along x, multiplies by
-// i * scale * M / f^2 and runs the two inverse x transforms of fx^a (a = 0, 1) into half slots.
-template <typename R, int N>
+// Fused forward-x / inverse-x pass of a second-order source: reads the (z-forward, y-forward)
+// transformed source from a half slot and completes the forward transform along x.  Gradient
+// form (HESS false, the 2LPT displacement): multiplies by i * scale * M / f^2 and runs the two
+// inverse x transforms of fx^a (a = 0, 1).  Hessian form (HESS true, the second-order tensor of
+// the third-order displacement): multiplies by scale * M / f^2 and runs the three inverse x
+// transforms of fx^a (a = 0, 1, 2), the outputs of the Hessian x pass.  Outputs: half slots.
+template <typename R, int N, bool HESS>
 __global__ void __launch_bounds__((Strided<R, N, +1>::T))
 k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
                const typename Cplx<R>::type* __restrict__ tw, R scale) {
@@ -310,10 +313,10 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
       const bool keep = ok[k] && n != N / 2 && y != N / 2 && f2 > R(0);
       const R m = keep ? scale / f2 : R(0);
       const V d = v[k][s];
-      v[k][s] = V{-d.y * m, d.x * m};
+      v[k][s] = HESS ? V{d.x * m, d.y * m} : V{-d.y * m, d.x * m};
     }
 #pragma unroll 1
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < (HESS ? 3 : 2); ++a) {
     V u[E::K0][E::R0];
 #pragma unroll
     for (int k = 0; k < E::K0; ++k)
@@ -331,6 +334,84 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
 }
 
 // ---------------------------------------------------------------------------------------------
+// Fused forward-x / inverse-x pass of the third-order displacement: four half slots in, the
+// (z-forward, y-forward) transforms of the divergence source s and of the transverse source
+// c = (cx, cy, cz); forward transforms along x; per mode
+//     psi_a = i scale M / f^2 (-f_a S + f_b C_d - f_d C_b),   (a, b, d) cyclic,
+// and the three inverse x transforms of psi_a into half slots (the y and z passes finish them).
+template <typename R, int N>
+__global__ void __launch_bounds__((Strided<R, N, +1>::T))
+k_xpass_lpt3(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
+             const typename Cplx<R>::type* __restrict__ tw, R scale) {
+  using S = Strided<R, N, +1>;
+  using V = typename S::V;
+  using E = typename S::E;
+  using EF = Engine<V, N, S::PS, 1, true, S::T, -1>;
+  constexpr int PS = S::PS, HZ = S::HZ, M = N / E::R0;
+  __shared__ V lds[E::LDS_ELEMS];
+  __shared__ V s_tw[tw_elems(N)];
+  const int t = threadIdx.x;
+  load_twiddles<N, S::T>(s_tw, tw, t);
+  const int bt = xcd_tile(blockIdx.x, S::GRID);
+  const int zt = bt % S::NZT;
+  const int y = bt / S::NZT;
+  const R fy = R(ifreq(y, N));
+  V v[4][E::K0][E::R0];
+  int zz[E::K0], jj[E::K0];
+  bool ok[E::K0];
+#pragma unroll
+  for (int k = 0; k < E::K0; ++k) {
+    int q, p, j;
+    E::first_layout(t, k, q, p, j, ok[k]);
+    const int z = zt * PS + p;
+    ok[k] = ok[k] && z < HZ;
+    zz[k] = z;
+    jj[k] = j;
+  }
+  // each source is loaded just before its forward transform (all four in flight at once would
+  // exceed the register budget of a 1024-thread workgroup)
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int k = 0; k < E::K0; ++k)
+#pragma unroll
+      for (int s = 0; s < E::R0; ++s)
+        v[c][k][s] = ok[k] ? in[c * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] : V{R(0), R(0)};
+    EF::run(v[c], lds, s_tw, t);
+  }
+  // psi3 components in place of (S, cx, cy), element by element
+#pragma unroll
+  for (int k = 0; k < E::K0; ++k)
+#pragma unroll
+    for (int s = 0; s < E::R0; ++s) {
+      const int n = jj[k] + s * M;
+      const R fx = R(ifreq(n, N)), fz = R(zz[k]);
+      const R f2 = fx * fx + fy * fy + fz * fz;
+      const bool keep = ok[k] && n != N / 2 && y != N / 2 && f2 > R(0);
+      const R m = keep ? scale / f2 : R(0);
+      const V sk = v[0][k][s], cx = v[1][k][s], cy = v[2][k][s], cz = v[3][k][s];
+      // i m (-f_a S + f_b c_d - f_d c_b): w = the bracket, then times i m
+      const V wx = V{fy * cz.x - fz * cy.x - fx * sk.x, fy * cz.y - fz * cy.y - fx * sk.y};
+      const V wy = V{fz * cx.x - fx * cz.x - fy * sk.x, fz * cx.y - fx * cz.y - fy * sk.y};
+      const V wz = V{fx * cy.x - fy * cx.x - fz * sk.x, fx * cy.y - fy * cx.y - fz * sk.y};
+      v[0][k][s] = V{-wx.y * m, wx.x * m};
+      v[1][k][s] = V{-wy.y * m, wy.x * m};
+      v[2][k][s] = V{-wz.y * m, wz.x * m};
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    E::run(v[a], lds, s_tw, t);
+#pragma unroll
+    for (int k = 0; k < E::K0; ++k)
+      if (ok[k]) {
+#pragma unroll
+        for (int s = 0; s < E::R0; ++s)
+          out[a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] = v[a][k][s];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // y pass, packed output.  Packed component c of the recipe is (a, b, cz): input half slot a,
 // fy^b before the transform, fz^cz after it; components (2q, 2q+1) go to packed slot q as
 // C = A + iB.  The Hessian pairs are ordered so that each pair reads as few inputs as possible
@@ -340,6 +421,8 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
 //   gradient (RECIPE 1), packed order x y | z:  (1,0,0) (0,1,0) | (0,0,1)
 //   gradient of the Hessian's x-pass outputs (RECIPE 3, v_max): RECIPE 1's components times i,
 //       which the gradient x pass applies itself but the Hessian x pass does not (TI)
+//   three finished components (RECIPE 4, the third-order displacement), packed order x y | z:
+//       (0,0,0) (1,0,0) | (2,0,0)
 // The z pass maps the packed order back to (xx, xy, xz, yy, yz, zz) and (x, y, z).
 template <int RECIPE> struct YRecipe;
 template <> struct YRecipe<0> {
@@ -354,6 +437,11 @@ template <> struct YRecipe<1> {
 };
 template <> struct YRecipe<3> : YRecipe<1> {
   static constexpr bool TI = true;
+};
+template <> struct YRecipe<4> {
+  static constexpr bool TI = false;
+  static constexpr int NIN = 3, NC = 3, Q = 2;
+  static constexpr int A[3] = {0, 1, 2}, B[3] = {0, 0, 0}, C[3] = {0, 0, 0};
 };
 
 template <typename R, int N, int RECIPE>
@@ -499,7 +587,7 @@ k_ypass_fwd(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::typ
 // ---------------------------------------------------------------------------------------------
 // z pass: inverse transform along z of Q packed slots (two real components each) and the
 // per-point epilogue.
-enum ZEpi { EPI_COLLAPSE = 0, EPI_STORE = 1, EPI_MU2 = 2, EPI_COLLAPSE_V = 3 };
+enum ZEpi { EPI_COLLAPSE = 0, EPI_STORE = 1, EPI_MU2 = 2, EPI_COLLAPSE_V = 3, EPI_LPT3 = 4 };
 
 template <typename R, int N, int Q, int EPI>
 struct ZPass {
@@ -524,7 +612,26 @@ struct ZArgs {
   const void* gin;  // EPI_COLLAPSE_V: the two packed gradient slots (y-pass recipe 3)
   void* vout;       // EPI_COLLAPSE_V: v_max [3][N^3] (R)
   double vscale;    // EPI_COLLAPSE_V: L / 2 pi
+  void* t6;         // EPI_MU2: when not null, the six components are stored to t6[6][N^3] (R);
+                    // EPI_LPT3: the first-order tensor T1 [6][N^3] read at each point
 };
+
+// Sources of the third-order displacement at one point from the first-order tensor a and the
+// second-order tensor b (xx, xy, xz, yy, yz, zz): the divergence
+//     sl = det(a) / 3 - (10/21) ((tr a)(tr b) - tr(a b)) / 2
+// and the curl c_i = eps_ijk (a b)_jk / 7.
+template <typename R>
+__device__ __forceinline__ void lpt3_sources(const R (&a)[6], const R (&b)[6], R& sl, R& cx, R& cy, R& cz) {
+  const R axx = a[0], axy = a[1], axz = a[2], ayy = a[3], ayz = a[4], azz = a[5];
+  const R bxx = b[0], bxy = b[1], bxz = b[2], byy = b[3], byz = b[4], bzz = b[5];
+  const R det = axx * (ayy * azz - ayz * ayz) - axy * (axy * azz - ayz * axz) + axz * (axy * ayz - ayy * axz);
+  const R trab = axx * bxx + ayy * byy + azz * bzz + R(2) * (axy * bxy + axz * bxz + ayz * byz);
+  const R mixed = R(0.5) * ((axx + ayy + azz) * (bxx + byy + bzz) - trab);
+  sl = det * R(1.0 / 3.0) - mixed * R(10.0 / 21.0);
+  cx = (axy * bxz + ayy * byz + ayz * bzz - axz * bxy - ayz * byy - azz * byz) * R(1.0 / 7.0);
+  cy = (axz * bxx + ayz * bxy + azz * bxz - axx * bxz - axy * byz - axz * bzz) * R(1.0 / 7.0);
+  cz = (axx * bxy + axy * byy + axz * byz - axy * bxx - ayy * bxy - ayz * bxz) * R(1.0 / 7.0);
+}
 
 template <typename R, int N, int Q, int EPI>
 __global__ void __launch_bounds__((ZPass<R, N, Q, EPI>::T))
@@ -643,6 +750,52 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
           if (c < args.nc) out[(size_t)c * VOL + idx] = comp(c, s);
       }
     }
+  } else if constexpr (EPI == EPI_LPT3) {
+    static_assert(Q == 3, "third-order sources need the six components of T2");
+    // sources of the third-order displacement at each point from T2 (this pass) and T1 (read),
+    // packed (sl + i cx), (cy + i cz) and transformed forward along z; the two real spectra of
+    // each packed line are separated and written to four half slots (sl, cx, cy, cz)
+    using EF = Engine<V, N, P, 1, false, Z::T, -1>;
+    static_assert(EF::K0 == 1 && EF::LDS_ELEMS <= E::LDS_ELEMS, "forward z tile: the inverse one's layout");
+    const R* t1 = static_cast<const R*>(args.t6);
+    constexpr size_t VOL = (size_t)N * N * N;
+    V w[2][R0];
+#pragma unroll
+    for (int s = 0; s < R0; ++s) {
+      const size_t idx = (size_t)lineL * N + j + s * M0;
+      R a6[6], b6[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        a6[c] = t1[c * VOL + idx];
+        b6[c] = comp(c, s);
+      }
+      R sl, cx, cy, cz;
+      lpt3_sources(a6, b6, sl, cx, cy, cz);
+      w[0][s] = V{sl, cx};
+      w[1][s] = V{cy, cz};
+    }
+    V* out = static_cast<V*>(args.out);
+    constexpr size_t HSLOT = (size_t)N * N * HZ;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      EF::run(*reinterpret_cast<V(*)[1][R0]>(&w[q]), lds, s_tw, t);
+#pragma unroll
+      for (int s = 0; s < R0; ++s) lds[EF::lds_index(0, p, j + s * M0)] = w[q][s];
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < R0 / 2; ++s) {
+        const int k = j + s * M0;
+        const V zk = lds[EF::lds_index(0, p, k)];
+        const V zn = lds[EF::lds_index(0, p, (N - k) % N)];
+        const V A = V{R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};   // (Z_k + conj Z_{N-k})/2
+        const V B = V{R(0.5) * (zk.y + zn.y), R(0.5) * (zn.x - zk.x)};   // (Z_k - conj Z_{N-k})/(2i)
+        if (line_ok) {
+          out[(size_t)(2 * q) * HSLOT + (size_t)line * HZ + k] = A;
+          out[(size_t)(2 * q + 1) * HSLOT + (size_t)line * HZ + k] = B;
+        }
+      }
+      __syncthreads();
+    }
   } else {
     static_assert(EPI == EPI_MU2 && Q == 3, "2LPT source needs the six components");
     // mu2 at each point, then a forward real-to-complex transform along z of line pairs
@@ -654,6 +807,17 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
       const int n = j + s * M0;
       const R xx = comp(0, s), xy = comp(1, s), xz = comp(2, s), yy = comp(3, s), yz = comp(4, s), zz = comp(5, s);
       const R mu2 = line_ok ? (xx * yy + xx * zz + yy * zz - xy * xy - xz * xz - yz * yz) : R(0);
+      if (args.t6 != nullptr && line_ok) {
+        R* t6 = static_cast<R*>(args.t6);
+        constexpr size_t VOL = (size_t)N * N * N;
+        const size_t idx = (size_t)line * N + n;
+        t6[idx] = xx;
+        t6[VOL + idx] = xy;
+        t6[2 * VOL + idx] = xz;
+        t6[3 * VOL + idx] = yy;
+        t6[4 * VOL + idx] = yz;
+        t6[5 * VOL + idx] = zz;
+      }
       reinterpret_cast<R*>(&lds[EF::lds_index(0, p >> 1, n)])[p & 1] = mu2;
     }
     __syncthreads();

@@ -22,10 +22,14 @@ struct SizeOps {
   // user half spectrum (2 outputs).  out = first workspace slot of the outputs.
   void (*xpass)(int mode, const void* dk, void* out, const void* wtab, const void* tw, double scale,
                 hipStream_t s);
-  // fused forward-x / inverse-x (2LPT): one input slot -> two output slots
-  void (*xpass_fwdinv)(const void* in, void* out, const void* tw, double scale, hipStream_t s);
+  // fused forward-x / inverse-x of a second-order source: one input slot -> two output slots
+  // (gradient, 2LPT) or three (hess: the Hessian x-pass outputs)
+  void (*xpass_fwdinv)(bool hess, const void* in, void* out, const void* tw, double scale, hipStream_t s);
+  // fused forward-x / inverse-x of the third-order displacement: four source slots -> three
+  void (*xpass_lpt3)(const void* in, void* out, const void* tw, double scale, hipStream_t s);
   // y pass: recipe 0 Hessian (3 half slots -> 3 packed slots), 1 gradient (2 half -> 2 packed),
-  // 2 forward (1 half -> 1 half), 3 gradient times i from the Hessian x pass (2 half -> 2 packed)
+  // 2 forward (1 half -> 1 half), 3 gradient times i from the Hessian x pass (2 half -> 2 packed),
+  // 4 three finished components (3 half -> 2 packed)
   void (*ypass)(int recipe, const void* in, void* out, const void* tw, hipStream_t s);
   // z pass (packed slots in) with the collapse epilogue at radius index r
   void (*zpass_collapse)(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain,
@@ -36,8 +40,12 @@ struct SizeOps {
                            int r, double sphere_gain, double vscale, hipStream_t s);
   // z pass storing nc = 6 (Hessian) or 3 (gradient) real components to out[nc][N^3]
   void (*zpass_store)(int nc, const void* in, const void* tw, void* out, hipStream_t s);
-  // z pass computing the 2LPT source and its forward transform along z into one slot
-  void (*zpass_mu2)(const void* in, const void* tw, void* out_slot, hipStream_t s);
+  // z pass computing the 2LPT source and its forward transform along z into one slot; the six
+  // tensor components are also stored to t6[6][N^3] when t6 is not null
+  void (*zpass_mu2)(const void* in, const void* tw, void* out_slot, void* t6, hipStream_t s);
+  // z pass of the second-order tensor with the third-order source epilogue: reads T1 [6][N^3],
+  // writes the z-forward transforms of (sl, cx, cy, cz) to four half slots
+  void (*zpass_lpt3)(const void* in, const void* t1, const void* tw, void* out_slots, hipStream_t s);
   void (*grf)(void* dk, uint64_t seed, double norm, double kf, double gamma, double ns, hipStream_t s);
   void (*reset)(void* F, uint8_t* ridx, hipStream_t s);
   // collapse redshift of count F values (growth table on the device, see k_redshift)

@@ -36,7 +36,8 @@ const char* const kClassNames[KC_COUNT] = {
     "grf",           "reset",          "xpass_hessian", "ypass_hessian", "zpass_collapse",
     "zpass_store",   "xpass_gradient", "ypass_gradient", "zpass_mu2",    "ypass_forward",
     "xpass_fwdinv",  "collapse_points", "prep",          "ypass_velocity", "zpass_collapse_v",
-    "zero",          "redshift"};
+    "zero",          "redshift",       "zpass_mu2_store", "xpass_fwdinv_hessian", "zpass_lpt3",
+    "xpass_lpt3",    "ypass_lpt3"};
 
 void fail(pin_status s, const std::string& m) { throw PinError(s, m); }
 
@@ -147,6 +148,7 @@ void plan_free(pin_plan p) {
   if (p->Y) (void)hipFree(p->Y);
   if (p->G) (void)hipFree(p->G);
   if (p->V) (void)hipFree(p->V);
+  if (p->L) (void)hipFree(p->L);
   if (p->growth) (void)hipFree(p->growth);
   delete p;
 }
@@ -234,13 +236,46 @@ void plan_displacements(pin_plan p, const void* dk, void* psi1, void* psi2, hipS
     const void* ones = p->window_row(p->nr_capacity);
     p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, ones, p->tw, 1.0, s); });
     p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
-    p->launch(KC_ZPASS_MU2, s, [&] { p->ops->zpass_mu2(p->Y, p->tw, p->xslot(0), s); });
+    p->launch(KC_ZPASS_MU2, s, [&] { p->ops->zpass_mu2(p->Y, p->tw, p->xslot(0), nullptr, s); });
     p->launch(KC_YPASS_FWD, s, [&] { p->ops->ypass(2, p->xslot(0), p->xslot(1), p->tw, s); });
     p->launch(KC_XPASS_FWDINV, s,
-              [&] { p->ops->xpass_fwdinv(p->xslot(1), p->Y, p->tw, (3.0 / 7.0) * lfac / n3, s); });
+              [&] { p->ops->xpass_fwdinv(false, p->xslot(1), p->Y, p->tw, (3.0 / 7.0) * lfac / n3, s); });
     p->launch(KC_YPASS_GRAD, s, [&] { p->ops->ypass(1, p->Y, p->X, p->tw, s); });
     p->launch(KC_ZPASS_STORE, s, [&] { p->ops->zpass_store(3, p->X, p->tw, psi2, s); });
   }
+}
+
+size_t lpt3_workspace_bytes(int n, bool fp64) {
+  const size_t rb = fp64 ? 8 : 4;
+  return 10 * (size_t)n * n * (n / 2) * 2 * rb;
+}
+
+void plan_lpt3_displacement(pin_plan p, const void* dk, void* psi3, hipStream_t s) {
+  if (p->L == nullptr) p->L = device_alloc(lpt3_workspace_bytes(p->n, p->fp64), "workspace L");
+  const double n3 = (double)p->n * p->n * p->n;
+  const double lfac = p->box / (2.0 * 3.14159265358979323846);
+  auto lslot = [&](int i) { return static_cast<char*>(p->L) + (size_t)i * p->slot_bytes; };
+  // T1 (unsmoothed Hessian of phi1) stored as six real fields in L[0..5], and mu2(T1) forward
+  // along z into L[6]; forward y into L[7]
+  prep_hessian_input(p, dk, s);
+  const void* ones = p->window_row(p->nr_capacity);
+  p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, ones, p->tw, 1.0, s); });
+  p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
+  p->launch(KC_ZPASS_MU2_STORE, s, [&] { p->ops->zpass_mu2(p->Y, p->tw, lslot(6), lslot(0), s); });
+  p->launch(KC_YPASS_FWD, s, [&] { p->ops->ypass(2, lslot(6), lslot(7), p->tw, s); });
+  // T2 (Hessian of phi2, lap phi2 = mu2): forward x, M / f^2 and the Hessian x outputs, then the
+  // Hessian y pass; its z pass forms the third-order sources with T1 and transforms them forward
+  // along z into L[6..9]
+  p->launch(KC_XPASS_FWDINV_HESS, s, [&] { p->ops->xpass_fwdinv(true, lslot(7), p->X, p->tw, 1.0 / n3, s); });
+  p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
+  p->launch(KC_ZPASS_LPT3, s, [&] { p->ops->zpass_lpt3(p->Y, lslot(0), p->tw, lslot(6), s); });
+  // sources forward along y into X[0..3], then forward x, the psi3 multipliers and the inverse
+  // x transforms into Y[0..2], the inverse y (packed) into X and the inverse z into psi3
+  for (int i = 0; i < 4; ++i)
+    p->launch(KC_YPASS_FWD, s, [&] { p->ops->ypass(2, lslot(6 + i), p->xslot(i), p->tw, s); });
+  p->launch(KC_XPASS_LPT3, s, [&] { p->ops->xpass_lpt3(p->X, p->Y, p->tw, lfac / n3, s); });
+  p->launch(KC_YPASS_LPT3, s, [&] { p->ops->ypass(4, p->Y, p->X, p->tw, s); });
+  p->launch(KC_ZPASS_STORE, s, [&] { p->ops->zpass_store(3, p->X, p->tw, psi3, s); });
 }
 
 }  // namespace pin

@@ -58,6 +58,11 @@ enum KernelClass {
   KC_ZPASS_COLLAPSE_V,
   KC_ZERO,
   KC_REDSHIFT,
+  KC_ZPASS_MU2_STORE,
+  KC_XPASS_FWDINV_HESS,
+  KC_ZPASS_LPT3,
+  KC_XPASS_LPT3,
+  KC_YPASS_LPT3,
   KC_COUNT
 };
 extern const char* const kClassNames[KC_COUNT];
@@ -87,6 +92,8 @@ struct pin_plan_s {
   void* Y = nullptr;      // 6 half slots (= 3 packed slots)
   void* G = nullptr;      // 1 half slot: the radius-independent Hessian input
   void* V = nullptr;      // 4 half slots (= 2 packed slots) for v_max, allocated on first use
+  void* L = nullptr;      // 10 half slots for the third-order displacement, allocated on first use:
+                          // T1 as six real fields, then four source slots
   void* growth = nullptr; // growth table (D then dD/dy, float64) after pin_plan_set_growth
   double growth_y0 = 0, growth_h = 0, growth_a_per_D = 0, growth_lom = 0;
   size_t slot_bytes = 0;
@@ -137,5 +144,7 @@ void plan_reset_v(pin_plan p, void* F, uint8_t* ridx, void* vmax, hipStream_t s)
 void plan_run_radii_v(pin_plan p, const void* dk, void* F, uint8_t* ridx, void* vmax, int r0, int r1, hipStream_t s);
 size_t velocity_workspace_bytes(int n, bool fp64);
 void plan_displacements(pin_plan p, const void* dk, void* psi1, void* psi2, hipStream_t s);
+size_t lpt3_workspace_bytes(int n, bool fp64);
+void plan_lpt3_displacement(pin_plan p, const void* dk, void* psi3, hipStream_t s);
 
 }  // namespace pin

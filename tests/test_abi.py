@@ -20,7 +20,7 @@ def test_header_declares_the_path():
     names = declared_functions()
     for must in ("pin_plan_create", "pin_plan_destroy", "pin_generate_field", "pin_collapse_times",
                  "pin_collapse_times_range", "pin_displacements", "pin_deformation_tensor",
-                 "pin_inverse_collapse_time"):
+                 "pin_inverse_collapse_time", "pin_lpt3_displacement", "pin_collapse_times_v"):
         assert must in names
 
 
@@ -61,6 +61,9 @@ def test_workspace_bytes_formula():
     got = B.pin_plan_workspace_bytes(B.make_desc(n, 1000.0, [float(nr - i) for i in range(nr)]))
     slot = n * n * (n // 2) * 8
     assert got == 11 * slot + n * 8 + n * (nr + 1) * 4
+    desc = B.make_desc(n, 1000.0, [1.0])
+    assert B.pin_plan_velocity_workspace_bytes(desc) == 4 * slot
+    assert B.pin_plan_lpt3_workspace_bytes(desc) == 10 * slot
 
 
 def test_status_strings():
