@@ -21,6 +21,8 @@ What it computes, in the paper's order (section "Collapse times"):
 * ``points``      -- deformation tensor, collapse times and displacements at single grid points
                      by direct summation, for grids too large for the full-grid functions.
 * ``growth``      -- the growing mode D(z) of flat LambdaCDM and the sigma^2 radius ladder.
+* ``fragment``    -- the sequential fragmentation of the collapsed medium into halos and
+                     filaments (section "Fragmentation"), with the readings in its header.
 * ``dft``         -- naive O(N^6) discrete Fourier transforms used to pin the library FFT.
 * ``philox``      -- the Philox4x32-10 counter-based generator, written from its published
                      definition (Salmon, Moraes, Dror & Shaw, SC'11).
@@ -28,4 +30,4 @@ What it computes, in the paper's order (section "Collapse times"):
 Everything is float64 NumPy/SciPy on CPU cores.
 """
 
-from . import philox, spectrum, field, hessian, collapse, run, dft, metrics, lpt3  # noqa: F401
+from . import philox, spectrum, field, hessian, collapse, run, dft, metrics, lpt3, fragment  # noqa: F401
