@@ -188,6 +188,37 @@ pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* ps
 pin_status pin_plan_lpt3_workspace_bytes(const pin_plan_desc* desc, size_t* bytes);
 pin_status pin_lpt3_displacement(pin_plan plan, const void* dk, void* psi3, hipStream_t stream);
 
+/* Fragmentation of the collapsed medium into halos (section "Fragmentation").  Particles (grid
+ * points) with F[q] >= f_min (f_min = 1/D at the output time, > 0) are taken in decreasing F
+ * (ties in increasing linear index) at D = 1/F; each looks at its six neighbours:
+ *   (i) none collapsed: a new halo; (ii) one halo touched: accreted if d < f_a R + f_ra +
+ *   f_s (R sigma(R) D)^1.7 (eq. accretion), then neighbouring filament particles join it, else a
+ *   filament particle; (iii) several halos: accretion on the halo of smallest d/R, then every
+ *   pair merged if d < f_m max(R1, R2) + f_rm (eq. merging), accretion retried after the mergers
+ *   if it failed; (iv) filaments only: a filament particle.
+ * d is the distance after Zel'dovich displacement, x = q + D vmax (vmax from pin_collapse_times_v,
+ * Mpc/h, converted to grid units), periodic minimum image; a halo sits at its founder's position
+ * plus the mean offset of its members plus D times their mean displacement; R = (3 N_h/4 pi)^(1/3)
+ * grid units; sigma(R) is the top-hat rms of the plan's linear field at R box/n Mpc/h (64 nodes per
+ * octave, linear in ln R); merged halos keep the id of the larger (smaller id on equal sizes).
+ * The result equals that of taking the particles one by one in this order (the GPU runs them in
+ * parallel rounds of particles whose neighbourhoods and halos do not overlap).
+ * F [N^3] and vmax [3][N^3] are device arrays of the plan's precision; label [N^3] (device,
+ * int32) receives -2 (F < f_min), -1 (filament) or the halo id (linear index of its founding
+ * particle); halo_size [N^3] (device, int32, may be NULL) receives N_h at each halo id and 0
+ * elsewhere; *n_halos (host) the number of halos.  params NULL means Table 1's values
+ * (pin_fragment_default_params).  Synchronous: returns when done (rounds are driven from the
+ * host).  The first call on a plan allocates pin_plan_fragment_workspace_bytes of device memory
+ * more, kept until pin_plan_destroy. */
+typedef struct {
+  double f_a, f_ra, f_s; /* eq. accretion */
+  double f_m, f_rm;      /* eq. merging   */
+} pin_fragment_params;
+void pin_fragment_default_params(pin_fragment_params* out);
+pin_status pin_plan_fragment_workspace_bytes(const pin_plan_desc* desc, size_t* bytes);
+pin_status pin_fragment(pin_plan plan, const void* F, const void* vmax, double f_min, const pin_fragment_params* params,
+                        int32_t* label, int32_t* halo_size, int* n_halos, hipStream_t stream);
+
 /* eq. F per point: the inverse collapse time of the ellipsoidal collapse model (the per-point
  * step of pin_collapse_times) for caller-given tensors.  T6 (device, [6][count] of the plan's
  * real type, components xx, xy, xz, yy, yz, zz) -> F (device, [count]).  Model: lambda_1 = the

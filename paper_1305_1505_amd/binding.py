@@ -46,6 +46,11 @@ class pin_plan_desc(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("ns", ctypes.c_double), ("prec", ctypes.c_int)]
 
 
+class pin_fragment_params(ctypes.Structure):
+    _fields_ = [("f_a", ctypes.c_double), ("f_ra", ctypes.c_double), ("f_s", ctypes.c_double),
+                ("f_m", ctypes.c_double), ("f_rm", ctypes.c_double)]
+
+
 class PinError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{lib.pin_status_string(status).decode()} ({status}): {message}")
@@ -77,6 +82,10 @@ _sig = {
     "pin_displacements": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pin_plan_lpt3_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
     "pin_lpt3_displacement": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pin_fragment_default_params": (None, [ctypes.POINTER(pin_fragment_params)]),
+    "pin_plan_fragment_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "pin_fragment": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(pin_fragment_params), _vp, _vp,
+                                    ctypes.POINTER(ctypes.c_int), _vp]),
     "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
     "pin_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -203,6 +212,26 @@ def pin_plan_lpt3_workspace_bytes(desc):
 
 def pin_lpt3_displacement(plan, dk, psi3, stream=0):
     _check(lib.pin_lpt3_displacement(plan, _vp(dk), _vp(psi3), _vp(stream)))
+
+
+def pin_fragment_default_params():
+    out = pin_fragment_params()
+    lib.pin_fragment_default_params(ctypes.byref(out))
+    return out
+
+
+def pin_plan_fragment_workspace_bytes(desc):
+    out = ctypes.c_size_t()
+    _check(lib.pin_plan_fragment_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def pin_fragment(plan, F, vmax, f_min, params, label, halo_size, stream=0):
+    """Returns the number of halos."""
+    nh = ctypes.c_int(0)
+    _check(lib.pin_fragment(plan, _vp(F), _vp(vmax), float(f_min), ctypes.byref(params) if params is not None else None,
+                            _vp(label), _vp(halo_size or None), ctypes.byref(nh), _vp(stream)))
+    return nh.value
 
 
 def pin_inverse_collapse_time(plan, T6, count, F, stream=0):
@@ -351,6 +380,15 @@ class Plan:
         pin_displacements(self.handle, dk.data_ptr(), p1.data_ptr() if p1 is not None else 0,
                           p2.data_ptr() if p2 is not None else 0, self._stream())
         return p1, p2
+
+    def fragment(self, F, vmax, f_min=1.0, params=None, want_sizes=True):
+        """(label int32 [N, N, N], halo_size int32 [N, N, N] or None, number of halos) -- pin_fragment."""
+        n = self.n
+        label = self.torch.empty((n, n, n), dtype=self.torch.int32, device="cuda")
+        sizes = self.torch.empty((n, n, n), dtype=self.torch.int32, device="cuda") if want_sizes else None
+        count = pin_fragment(self.handle, F.data_ptr(), vmax.data_ptr(), f_min, params, label.data_ptr(),
+                             sizes.data_ptr() if sizes is not None else 0, self._stream())
+        return label, sizes, count
 
     def lpt3_displacement(self, dk):
         """psi3 (3, N, N, N) at D = 1 in Mpc/h (pin_lpt3_displacement)."""

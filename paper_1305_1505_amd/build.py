@@ -48,6 +48,9 @@ def build(jobs=None, verbose=False):
             obj = os.path.join(BUILD, f"inst_{fp64}_{n}.o")
             tasks.append([HIPCC, *COMMON, f"-DPIN_INST_N={n}", f"-DPIN_INST_FP64={fp64}",
                           "-c", os.path.join(CSRC, "inst.hip"), "-o", obj])
+    # fragmentation: float64 decisions in the order the method states them, no contraction
+    tasks.append([HIPCC, *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "fragment.hip"),
+                  "-o", os.path.join(BUILD, "fragment.o")])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         tasks.append([HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])

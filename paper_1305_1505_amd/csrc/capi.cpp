@@ -1,6 +1,8 @@
 // C ABI of libpin (include/pin.h): argument validation around the plan operations of plan.cpp.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <initializer_list>
 #include <vector>
 
 #include "pin.h"
@@ -212,6 +214,46 @@ pin_status pin_displacements(pin_plan plan, const void* dk, void* psi1, void* ps
     if (psi1) check_device_range(psi1, 3 * plan->real_field_bytes(), "psi1");
     if (psi2) check_device_range(psi2, 3 * plan->real_field_bytes(), "psi2");
     plan_displacements(plan, dk, psi1, psi2, stream);
+  });
+}
+
+void pin_fragment_default_params(pin_fragment_params* out) {
+  if (out == nullptr) return;
+  out->f_a = 0.285;
+  out->f_ra = 0.180;
+  out->f_s = 0.060;
+  out->f_m = 0.350;
+  out->f_rm = 0.700;
+}
+
+pin_status pin_plan_fragment_workspace_bytes(const pin_plan_desc* desc, size_t* bytes) {
+  return guarded([&] {
+    validate_desc(desc);
+    if (bytes == nullptr) fail(PIN_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = fragment_workspace_bytes(desc->n);
+  });
+}
+
+pin_status pin_fragment(pin_plan plan, const void* F, const void* vmax, double f_min, const pin_fragment_params* params,
+                        int32_t* label, int32_t* halo_size, int* n_halos, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (!(f_min > 0.0) || !std::isfinite(f_min)) fail(PIN_ERR_INVALID_ARG, "f_min must be positive and finite");
+    pin_fragment_params prm;
+    pin_fragment_default_params(&prm);
+    if (params) prm = *params;
+    for (double c : {prm.f_a, prm.f_ra, prm.f_s, prm.f_m, prm.f_rm})
+      if (!(c >= 0.0) || !std::isfinite(c)) fail(PIN_ERR_INVALID_ARG, "fragmentation constants must be finite and >= 0");
+    if (n_halos == nullptr) fail(PIN_ERR_INVALID_ARG, "n_halos is NULL");
+    check_device_range(F, plan->real_field_bytes(), "F");
+    check_device_range(vmax, 3 * plan->real_field_bytes(), "vmax");
+    const size_t vol = (size_t)plan->n * plan->n * plan->n;
+    check_device_range(label, vol * sizeof(int32_t), "label");
+    if (halo_size) check_device_range(halo_size, vol * sizeof(int32_t), "halo_size");
+    fragment_prepare(plan->frag, plan->n, plan->box, plan->amplitude, plan->gamma, plan->ns, stream);
+    const FragParams fp{prm.f_a, prm.f_ra, prm.f_s, prm.f_m, prm.f_rm};
+    *n_halos = fragment_run(plan->frag, plan->fp64, plan->n, F, vmax, plan->n / plan->box, f_min, fp, label,
+                            halo_size, stream);
   });
 }
 

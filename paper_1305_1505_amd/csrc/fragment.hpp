@@ -1,0 +1,56 @@
+// Fragmentation of the collapsed medium into halos (section "Fragmentation"): host-side
+// interface of fragment.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace pin {
+
+struct FragParams {
+  double fa, fra, fs, fm, frm;   // eq. accretion and eq. merging constants (Table 1)
+};
+
+// Device workspace of one fragmentation call on an N^3 grid (owned by the plan, kept between
+// calls) and the host tables it needs.
+struct FragWorkspace {
+  size_t vol = 0;
+  void* block = nullptr;          // one allocation holding everything below
+  size_t bytes = 0;
+  uint64_t* keys[2] = {nullptr, nullptr};
+  int32_t* vals[2] = {nullptr, nullptr};
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  int32_t* parent = nullptr;
+  int32_t* hn = nullptr;
+  double* hs = nullptr;           // [6][vol]: sums of offsets (3) and of displacements (3)
+  unsigned long long* res_cell = nullptr;
+  unsigned long long* res_halo = nullptr;
+  int32_t* items = nullptr;       // per window slot: count + up to 6 halo ids
+  int32_t* ctl = nullptr;         // head, next head, error, participant count
+  double* rtab = nullptr;         // halo radius for N_h = 1..kRadiusTable
+  double* stab = nullptr;         // sigma(R) nodes
+  int stab_n = 0;
+  double s_r0 = 0, s_step = 0;
+  int32_t* host_ctl = nullptr;    // pinned mirror of ctl
+};
+
+// Bytes of the workspace for an N^3 grid.
+size_t fragment_workspace_bytes(int n);
+
+// Allocate (first call) and fill the radius table and the sigma nodes (top-hat rms of the linear
+// field at z = 0, 64 nodes per octave in R from the radius of one particle); returns on completion.
+void fragment_prepare(FragWorkspace& w, int n, double box, double amplitude, double gamma, double ns,
+                      hipStream_t s);
+void fragment_free(FragWorkspace& w);
+
+// Run the fragmentation: F [vol] and v [3][vol] of the plan's precision (v in Mpc/h, converted to
+// grid units with uscale = N / L); label [vol] and optional halo_size [vol] are written.  Returns
+// the number of halos.  Synchronous: the rounds are driven from the host.
+int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* v, double uscale, double f_min,
+                 const FragParams& prm, int32_t* label, int32_t* halo_size, hipStream_t s);
+
+}  // namespace pin

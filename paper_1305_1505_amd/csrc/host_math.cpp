@@ -1,7 +1,9 @@
 // Host-side float64 tables and constants (spectrum normalisation, twiddles, windows).
 #include "host_math.hpp"
 
+#include <algorithm>
 #include <cmath>
+#include <thread>
 
 namespace pin {
 
@@ -77,6 +79,45 @@ double sigma2_tophat_unit(double radius, double gamma, double ns) {
     total += 0.5 * h * s;
   }
   return total / (2.0 * kPi * kPi);
+}
+
+std::vector<double> tophat_sigma_nodes(double r0, double step, int count, double amplitude, double gamma, double ns) {
+  static const GaussLegendre gl;
+  const double a = std::log(1e-7), b = std::log(1e3);
+  const int panels = 4000;
+  const double h = (b - a) / panels;
+  std::vector<double> kk((size_t)panels * 16), base((size_t)panels * 16);
+  for (int p = 0; p < panels; ++p) {
+    const double mid = a + (p + 0.5) * h;
+    for (int i = 0; i < 16; ++i) {
+      const double k = std::exp(mid + 0.5 * h * gl.x[i]);
+      const double t = bbks_transfer(k, gamma);
+      kk[(size_t)p * 16 + i] = k;
+      base[(size_t)p * 16 + i] = 0.5 * h * gl.w[i] * k * k * k * std::pow(k, ns) * t * t;
+    }
+  }
+  std::vector<double> out((size_t)count);
+  auto work = [&](int first, int stride) {
+    for (int c = first; c < count; c += stride) {
+      const double r = r0 * std::exp(c * step);
+      double total = 0.0;
+      for (int p = 0; p < panels; ++p) {
+        double sp = 0.0;
+        for (int i = 0; i < 16; ++i) {
+          const double w = tophat_window(kk[(size_t)p * 16 + i] * r);
+          sp += base[(size_t)p * 16 + i] * w * w;
+        }
+        total += sp;
+      }
+      out[(size_t)c] = std::sqrt(amplitude * total / (2.0 * kPi * kPi));
+    }
+  };
+  const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> threads;
+  for (int t = 1; t < nt; ++t) threads.emplace_back(work, t, nt);
+  work(0, nt);
+  for (auto& t : threads) t.join();
+  return out;
 }
 
 double sigma2_gaussian_unit(double radius, double gamma, double ns) {

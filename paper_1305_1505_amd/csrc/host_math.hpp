@@ -12,6 +12,10 @@ double tophat_window(double x);
 // sigma^2(R) = 1/(2 pi^2) Int k^2 P(k) W_TH(kR)^2 dk for P = k^ns T^2 (unit amplitude), by
 // composite 16-point Gauss-Legendre quadrature in ln k over [1e-7, 1e3] h/Mpc.
 double sigma2_tophat_unit(double radius, double gamma, double ns);
+// sigma(R_k) = sqrt(amplitude * sigma2_tophat_unit(R_k)) at R_k = r0 exp(k step) Mpc/h, k < count
+// (the same quadrature, with the radius-independent part of the integrand evaluated once and the
+// nodes spread over host threads).
+std::vector<double> tophat_sigma_nodes(double r0, double step, int count, double amplitude, double gamma, double ns);
 // sigma^2(R) with the Gaussian window, 1/(2 pi^2) Int k^2 P(k) exp(-k^2 R^2) dk (unit amplitude).
 double sigma2_gaussian_unit(double radius, double gamma, double ns);
 // Radii in cells, largest first from r_max, each with sigma^2 10^dex times the previous one's

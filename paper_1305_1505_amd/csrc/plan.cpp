@@ -149,6 +149,7 @@ void plan_free(pin_plan p) {
   if (p->G) (void)hipFree(p->G);
   if (p->V) (void)hipFree(p->V);
   if (p->L) (void)hipFree(p->L);
+  fragment_free(p->frag);
   if (p->growth) (void)hipFree(p->growth);
   delete p;
 }

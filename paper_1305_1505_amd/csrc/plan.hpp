@@ -8,6 +8,7 @@
 #include <utility>
 #include <vector>
 
+#include "fragment.hpp"
 #include "errors.hpp"
 #include "ops.hpp"
 #include "pin.h"
@@ -92,6 +93,7 @@ struct pin_plan_s {
   void* Y = nullptr;      // 6 half slots (= 3 packed slots)
   void* G = nullptr;      // 1 half slot: the radius-independent Hessian input
   void* V = nullptr;      // 4 half slots (= 2 packed slots) for v_max, allocated on first use
+  pin::FragWorkspace frag;  // fragmentation workspace, allocated on first use
   void* L = nullptr;      // 10 half slots for the third-order displacement, allocated on first use:
                           // T1 as six real fields, then four source slots
   void* growth = nullptr; // growth table (D then dD/dy, float64) after pin_plan_set_growth

@@ -1,0 +1,152 @@
+"""Fragmentation on the GPU (pin_fragment) against the sequential oracle (oracle.fragment),
+through the C ABI (GPU tests).
+
+Both sides take the same F_max and v_max: the oracle's, from its own seeded field, rounded to the
+plan's precision (so that the order of the particles and every displacement are the same
+numbers on both sides).  The labels must then agree exactly -- particle by particle, halo ids
+included -- and so must the halo sizes: the decisions are taken in float64 on both sides with the
+same operations; the only inputs computed differently are the sigma(R) nodes (two quadratures of
+the same integral, equal to ~1e-12), which cannot move a decision unless a distance falls within
+that of its threshold.  At the benchmark size the result is checked through invariants and
+repeatability.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import field, fragment as FR, run
+from paper_1305_1505_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_inputs(n, box, seed, n_radii):
+    radii = list(np.geomspace(20.0, 0.75, n_radii))
+    dk = field.linear_field(seed, n, box, W.SIGMA8, W.GAMMA, W.NS)
+    F, _, v = run.collapse_times_with_velocity(dk, radii, box)
+    return F.ravel(), v.reshape(3, -1), radii
+
+
+def _run_both(lib, n, box, seed, prec, f_min, n_radii=12):
+    import torch
+
+    F, v, radii = oracle_inputs(n, box, seed, n_radii)
+    dt = np.float64 if prec == lib.PIN_FP64 else np.float32
+    Fq, vq = F.astype(dt), v.astype(dt)
+    plan = lib.Plan(n, box, radii, sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=prec)
+    tF = torch.from_numpy(Fq.reshape(n, n, n)).cuda()
+    tv = torch.from_numpy(vq.reshape(3, n, n, n)).cuda()
+    label, sizes, count = plan.fragment(tF, tv, f_min)
+    torch.cuda.synchronize()
+    label, sizes = label.cpu().numpy().ravel(), sizes.cpu().numpy().ravel()
+    plan.close()
+    print(f"[fragment] n={n} f_min={f_min}: {count} halos, {int(np.sum(label == -1))} filament, "
+          f"{int(np.sum(label >= 0))} in halos", flush=True)
+    sigma = FR.SigmaTable(n, box, W.SIGMA8, W.GAMMA, W.NS, nh_max=n ** 3)
+    ref, ref_sizes = FR.fragment(Fq.astype(np.float64), vq.astype(np.float64) * (n / box), f_min, n, sigma)
+    return label, sizes, count, ref, ref_sizes
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,box,seed,f_min", [(32, 50.0, 11, 1.0), (48, 75.0, 12, 1.5), (64, 100.0, 13, 1.0)])
+def test_fragment_fp32_matches_oracle(lib, n, box, seed, f_min):
+    label, sizes, count, ref, ref_sizes = _run_both(lib, n, box, seed, lib.PIN_FP32, f_min)
+    assert count == len(ref_sizes) and count > 1
+    assert np.array_equal(label, ref)
+    expect = np.zeros(n ** 3, dtype=np.int64)
+    for h, s in ref_sizes.items():
+        expect[h] = s
+    assert np.array_equal(sizes, expect)
+
+
+@pytest.mark.timeout(600)
+def test_fragment_fp64_matches_oracle(lib):
+    label, sizes, count, ref, ref_sizes = _run_both(lib, 32, 50.0, 21, lib.PIN_FP64, 1.0)
+    assert count == len(ref_sizes)
+    assert np.array_equal(label, ref)
+
+
+def test_fragment_spheres(lib):
+    """The hand-built cases of the oracle's pins: one converging sphere is one halo; a diverging one
+    a peak and filaments."""
+    import torch
+
+    n, box = 16, 16.0      # one Mpc/h per cell: v in Mpc/h equals u in cells
+    i = np.arange(n ** 3)
+    q = np.stack([i // (n * n), (i // n) % n, i % n]).astype(np.float64)
+    d = q - 8.0
+    F = 2.0 - 0.02 * np.sum(d * d, axis=0)
+    plan = lib.Plan(n, box, [1.0], sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=lib.PIN_FP64)
+    for sign, halos in ((-1.0, 1), (1.0, 1)):
+        u = sign * d * F
+        label, sizes, count = plan.fragment(torch.from_numpy(F.reshape(n, n, n)).cuda(),
+                                            torch.from_numpy(u.reshape(3, n, n, n)).cuda(), 1.0)
+        label = label.cpu().numpy().ravel()
+        peak = 8 * n * n + 8 * n + 8
+        assert count == halos and label[peak] == peak
+        collapsed = F >= 1.0
+        if sign < 0:
+            assert np.all(label[collapsed] == peak) and int(sizes.cpu().numpy().ravel()[peak]) == int(collapsed.sum())
+        else:
+            rest = collapsed.copy()
+            rest[peak] = False
+            assert np.all(label[rest] == FR.FILAMENT)
+        assert np.all(label[~collapsed] == FR.NOT_COLLAPSED)
+    plan.close()
+
+
+def test_fragment_argument_errors(lib):
+    import torch
+
+    plan = lib.Plan(16, 16.0, [1.0], sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=lib.PIN_FP32)
+    F = torch.ones((16, 16, 16), dtype=torch.float32, device="cuda")
+    v = torch.zeros((3, 16, 16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.PinError) as e:
+        plan.fragment(F, v, 0.0)
+    assert e.value.status == lib.PIN_ERR_INVALID_ARG
+    label = torch.empty((16, 16, 16), dtype=torch.int32, device="cuda")
+    for args in ((0, v.data_ptr(), label.data_ptr()), (F.data_ptr(), 0, label.data_ptr()),
+                 (F.data_ptr(), v.data_ptr(), 0)):
+        with pytest.raises(lib.PinError) as e:
+            lib.pin_fragment(plan.handle, args[0], args[1], 1.0, None, args[2], 0)
+        assert e.value.status == lib.PIN_ERR_INVALID_ARG
+    bad = lib.pin_fragment_default_params()
+    bad.f_m = float("nan")
+    with pytest.raises(lib.PinError):
+        lib.pin_fragment(plan.handle, F.data_ptr(), v.data_ptr(), 1.0, bad, label.data_ptr(), 0)
+    plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_fragment_c512_invariants(lib):
+    """The benchmark workload: F_max and v_max from pin_collapse_times_v, fragmentation at z = 0
+    (f_min = 1): labels partition the collapsed particles, sizes count the members, every halo id
+    is a member of its own halo, and a second run is bit-identical."""
+    import torch
+
+    cfg = W.CONFIGS["c512_fp32"]
+    n = cfg["n"]
+    plan = lib.Plan(n, cfg["box"], W.config_radii(cfg), sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=lib.PIN_FP32)
+    dk = plan.generate_field(cfg["seed"])
+    F, R, v = plan.collapse_times_v(dk)
+    del dk, R
+    label, sizes, count = plan.fragment(F, v, 1.0)
+    label2, sizes2, count2 = plan.fragment(F, v, 1.0)
+    assert count == count2 and bool(torch.equal(label, label2)) and bool(torch.equal(sizes, sizes2))
+    del label2, sizes2
+    collapsed = F >= 1.0
+    assert bool(torch.equal(label == -2, ~collapsed))
+    in_halo = label >= 0
+    flat = label.view(-1)
+    members = torch.bincount(flat[flat >= 0].long(), minlength=n ** 3)
+    s = sizes.view(-1).long()
+    assert bool(torch.equal(members, s))
+    roots = torch.nonzero(s > 0).view(-1)
+    assert roots.numel() == count
+    assert bool(torch.equal(flat[roots].long(), roots))
+    print(f"[fragment] 512^3: {count} halos, {int(in_halo.sum())} particles in halos, "
+          f"{int((label == -1).sum())} filament, largest {int(s.max())}", flush=True)
+    plan.close()
