@@ -299,7 +299,19 @@ def main():
 
     collapse_v()
     vel_ms = timed(collapse_v)
-    del vmax
+    # fragmentation at z = 0 (f_min = 1) of that F_max and v_max, after one warm-up call (which
+    # allocates its workspace and tables); synchronous, so timed on the host clock too
+    label = torch.empty((n, n, n), dtype=torch.int32, device="cuda")
+    halo_size = torch.empty((n, n, n), dtype=torch.int32, device="cuda")
+    B.pin_fragment(plan.handle, F.data_ptr(), vmax.data_ptr(), 1.0, None, label.data_ptr(), halo_size.data_ptr(), stream)
+    t0f = time.perf_counter()
+    n_halos = B.pin_fragment(plan.handle, F.data_ptr(), vmax.data_ptr(), 1.0, None, label.data_ptr(),
+                             halo_size.data_ptr(), stream)
+    frag_ms = 1000.0 * (time.perf_counter() - t0f)
+    frag = {"ms": round(frag_ms, 2), "halos": n_halos, "particles_in_halos": int((label >= 0).sum()),
+            "filament": int((label == -1).sum()), "collapsed": int((label != -2).sum()),
+            "largest_halo": int(halo_size.max())}
+    del vmax, label, halo_size
     # collapse redshift of every point (flat LambdaCDM, Omega_m 0.25): 2 x real bytes per point
     zc = torch.empty_like(F)
     B.pin_plan_set_growth(plan.handle, 0.25, stream)
@@ -385,6 +397,7 @@ def main():
         "field_ms": round(field_ms, 3),
         "displacements_ms": round(disp_ms, 3),
         "lpt3_ms": round(lpt3_ms, 3),
+        "fragment": frag,
         "path_roofline": path_roofline,
         "fp64": fp64,
         "roofline": roofline,
