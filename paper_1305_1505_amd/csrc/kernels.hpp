@@ -104,8 +104,9 @@ template <typename R> __device__ __forceinline__ R powf_int(R f, int e) {
   return e == 0 ? R(1) : (e == 1 ? f : f * f);
 }
 
-// Streaming store: the line is not retained in L2 (the y pass writes twice what it reads; plain
-// stores would evict the input tiles it re-reads).
+// Streaming store: the line is not retained in the caches.  Used for every output that the next
+// pass reads only after much other traffic: plain stores would leave dirty lines that evict the
+// tiles a pass re-reads, or that the next pass has to write back while it runs.
 template <typename V> __device__ __forceinline__ void st_stream(V* p, V v) {
   using R = decltype(v.x);
   typedef R R2 __attribute__((ext_vector_type(2)));
@@ -152,7 +153,7 @@ __global__ void k_prep(const typename Cplx<R>::type* __restrict__ dk, typename C
       out = V{d.x * m, d.y * m};
     }
   }
-  g0[i] = out;
+  st_stream(&g0[i], out);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -260,7 +261,7 @@ k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
       if (ok[k]) {
 #pragma unroll
         for (int s = 0; s < E::R0; ++s)
-          out[a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] = u[k][s];
+          st_stream(out + a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k], u[k][s]);
       }
   }
 }
@@ -330,7 +331,7 @@ k_xpass_fwdinv(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
       if (ok[k]) {
 #pragma unroll
         for (int s = 0; s < E::R0; ++s)
-          out[a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] = u[k][s];
+          st_stream(out + a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k], u[k][s]);
       }
   }
 }
@@ -408,7 +409,7 @@ k_xpass_lpt3(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::ty
       if (ok[k]) {
 #pragma unroll
         for (int s = 0; s < E::R0; ++s)
-          out[a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k]] = v[a][k][s];
+          st_stream(out + a * S::HSLOT + ((size_t)(jj[k] + s * M) * N + y) * HZ + zz[k], v[a][k][s]);
       }
   }
 }
@@ -582,7 +583,7 @@ k_ypass_fwd(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::typ
   for (int k = 0; k < E::K0; ++k)
     if (ok[k]) {
 #pragma unroll
-      for (int s = 0; s < E::R0; ++s) out[((size_t)x * N + jj[k] + s * M) * HZ + zz[k]] = v[k][s];
+      for (int s = 0; s < E::R0; ++s) st_stream(out + ((size_t)x * N + jj[k] + s * M) * HZ + zz[k], v[k][s]);
     }
 }
 
@@ -750,7 +751,7 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
         const size_t idx = (size_t)line * N + j + s * M0;
 #pragma unroll
         for (int c = 0; c < 2 * Q; ++c)
-          if (c < args.nc) out[(size_t)c * VOL + idx] = comp(c, s);
+          if (c < args.nc) __builtin_nontemporal_store(comp(c, s), &out[(size_t)c * VOL + idx]);
       }
     }
   } else if constexpr (EPI == EPI_LPT3) {
@@ -849,8 +850,8 @@ k_zpass(const typename Cplx<R>::type* __restrict__ in, const typename Cplx<R>::t
       const V a = V{R(0.5) * (zk.x + zn.x), R(0.5) * (zk.y - zn.y)};   // (Z_k + conj Z_{N-k})/2
       const V b = V{R(0.5) * (zk.y + zn.y), R(0.5) * (zn.x - zk.x)};   // (Z_k - conj Z_{N-k})/(2i)
       const int l0 = blockIdx.x * P + 2 * u;
-      if (l0 < Z::LINES) out[(size_t)l0 * HZ + k] = a;
-      if (l0 + 1 < Z::LINES) out[(size_t)(l0 + 1) * HZ + k] = b;
+      if (l0 < Z::LINES) st_stream(out + (size_t)l0 * HZ + k, a);
+      if (l0 + 1 < Z::LINES) st_stream(out + (size_t)(l0 + 1) * HZ + k, b);
     }
   }
 }
