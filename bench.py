@@ -77,7 +77,17 @@ def cpu_baseline(sample_n=64, radius_stride=1):
             "seconds": dt,
             "sample": f"{sample_n}^3 grid at the workload's cell size ({box:g} Mpc/h), "
                       f"{len(radii)} of its {cfg['n_radii']} radii, field + collapse + ZA/2LPT, "
-                      f"float64 NumPy/SciPy, {os.cpu_count()} host cores visible"}
+                      f"float64 NumPy/SciPy, {os.cpu_count()} host cores visible ({_cpu_model()})"}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def serve_bench(B, W, full=False):

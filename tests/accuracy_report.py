@@ -1,10 +1,11 @@
 """Accuracy of the HIP path against the FP64 oracle on every workload: max and RMS relative error
-of F_max and of the ZA and 2LPT displacements, and the fraction of grid points whose collapse
+of F_max and of the ZA, 2LPT and 3LPT displacements, and the fraction of grid points whose collapse
 radius R_max differs (float32 and float64 plans).
 
     python tests/accuracy_report.py [--workers 16] [--out report.json]
 
-Full grids where the oracle fits the run time (64^3, 256^3; displacements also at 512^3);
+Full grids where the oracle fits the run time (64^3, 256^3; displacements, 3LPT included, also at
+512^3);
 sampled grid points (oracle.points) for F at 512^3 and 768^3 and psi1 at 768^3.  The oracle runs
 in a pool of worker processes started before this process touches the GPU; radii are split
 between workers and their partial maxima merged with the rule of the running maximum (larger F
@@ -25,7 +26,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-from oracle import field, metrics, points, run  # noqa: E402
+from oracle import field, lpt3, metrics, points, run  # noqa: E402
 from paper_1305_1505_amd import workloads as W  # noqa: E402
 
 POINTS = {"c512_fp32": 64, "c768_fp32": 32}
@@ -44,6 +45,10 @@ def job_radii(name, r0, r1):
 
 def job_disp(name):
     return ("disp", name, run.displacements(_field(name), W.CONFIGS[name]["box"]))
+
+
+def job_lpt3(name):
+    return ("lpt3", name, lpt3.lpt3_displacement(_field(name), W.CONFIGS[name]["box"]))
 
 
 def job_points(name, pts):
@@ -92,6 +97,10 @@ def gpu_outputs(lib, name, prec, pts=None, want_disp=True):
         if p2 is not None:
             out["psi2"] = at(p2)
         del p1, p2
+        if pts is None:
+            p3 = plan.lpt3_displacement(dk)
+            out["psi3"] = at(p3)
+            del p3
     del dk
     plan.close()
     torch.cuda.synchronize()
@@ -155,6 +164,7 @@ def main():
     pending.append(pool.apply_async(job_radii, ("c64_fp64", 0, len(W.config_radii(W.CONFIGS["c64_fp64"])))))
     for name in ("c64_fp64", "c256_fp32", "c512_fp32"):
         pending.append(pool.apply_async(job_disp, (name,)))
+        pending.append(pool.apply_async(job_lpt3, (name,)))
     for r0 in range(len(W.config_radii(W.CONFIGS["c256_fp32"]))):
         pending.append(pool.apply_async(job_radii, ("c256_fp32", r0, r0 + 1)))
     sampled = {name: sample_points(name) for name in SAMPLED}
@@ -164,13 +174,15 @@ def main():
             pending.append(pool.apply_async(job_points, (name, pts[i:i + per])))
     print(f"[accuracy] {len(pending)} oracle jobs queued", flush=True)
 
-    radii_parts, disp, pts_res = {}, {}, {}
+    radii_parts, disp, pts_res, psi3 = {}, {}, {}, {}
     for job in pending:
         res = job.get()
         if res[0] == "radii":
             radii_parts.setdefault(res[1], []).append((res[2], res[3]))
         elif res[0] == "disp":
             disp[res[1]] = res[2]
+        elif res[0] == "lpt3":
+            psi3[res[1]] = res[2]
         else:
             pts_res.setdefault(res[1], []).append(res[2:])
         print(f"[accuracy] oracle {res[0]} {res[1]} done {time.time() - t0:.0f} s", flush=True)
@@ -203,11 +215,14 @@ def main():
             row.update(psi1_rel_rms=metrics.rel_rms(g["psi1"], r1), psi1_rel_max=metrics.rel_max(g["psi1"], r1),
                        psi2_rel_rms=metrics.rel_rms(g["psi2"], r2), psi2_rel_max=metrics.rel_max(g["psi2"], r2),
                        psi_points="all")
+        if name in psi3 and "psi3" in g:
+            r3 = psi3[name]
+            row.update(psi3_rel_rms=metrics.rel_rms(g["psi3"], r3), psi3_rel_max=metrics.rel_max(g["psi3"], r3))
         rows.append(row)
         print("[accuracy] " + json.dumps(row), flush=True)
 
     keys = ["config", "F_rel_rms", "F_rel_max", "R_mismatch", "F_points", "psi1_rel_rms", "psi1_rel_max",
-            "psi2_rel_rms", "psi2_rel_max", "psi_points"]
+            "psi2_rel_rms", "psi2_rel_max", "psi3_rel_rms", "psi3_rel_max", "psi_points"]
     fmt = lambda v: f"{v:.2e}" if isinstance(v, float) else str(v)
     print("| " + " | ".join(keys) + " |")
     print("|" + "---|" * len(keys))

@@ -62,6 +62,19 @@ def test_fragment_fp32_matches_oracle(lib, n, box, seed, f_min):
     assert np.array_equal(sizes, expect)
 
 
+@pytest.mark.timeout(900)
+def test_fragment_fp32_matches_oracle_128(lib):
+    """128^3 (200 Mpc/h): ~8e5 collapsed particles, halos of a few hundred particles, many mergers."""
+    n = 128
+    label, sizes, count, ref, ref_sizes = _run_both(lib, n, 200.0, 14, lib.PIN_FP32, 1.0, n_radii=8)
+    assert count == len(ref_sizes)
+    assert np.array_equal(label, ref)
+    expect = np.zeros(n ** 3, dtype=np.int64)
+    for h, sz in ref_sizes.items():
+        expect[h] = sz
+    assert np.array_equal(sizes, expect)
+
+
 @pytest.mark.timeout(600)
 def test_fragment_fp64_matches_oracle(lib):
     label, sizes, count, ref, ref_sizes = _run_both(lib, 32, 50.0, 21, lib.PIN_FP64, 1.0)
