@@ -111,24 +111,39 @@ constexpr int tw_elems(int N) {
   return e > 0 ? e : 1;
 }
 
-// Fill the per-stage table from the N-entry table exp(2 pi i m/N) in global memory (one stage
-// per instantiation, so that every index is a compile-time constant).
-template <int N, int T, int S_, typename V>
-__device__ __forceinline__ void fill_stage_twiddles(V* __restrict__ s_tw, const V* __restrict__ tw, int t) {
+// Source index in the N-entry table of per-stage entry i (stage found by compile-time recursion,
+// so that no stage parameter is indexed at run time).
+template <int N, int S_> __device__ __forceinline__ int tw_source(int i) {
   constexpr Factor f = factorize(N);
-  if constexpr (S_ < f.n) {
+  if constexpr (S_ >= f.n) {
+    return 0;
+  } else {
     constexpr int ns = radix_prefix(f, S_), R = f.r[S_], off = tw_stage_offset(f, S_);
-    for (int i = t; i < (R - 1) * ns; i += T) {
-      const int x = i / ns + 1, kk = i % ns;
-      s_tw[off + i] = tw[x * kk * (N / (ns * R))];
+    if (i < off + (R - 1) * ns) {
+      const int l = i - off;
+      return (l / ns + 1) * (l % ns) * (N / (ns * R));
     }
-    fill_stage_twiddles<N, T, S_ + 1>(s_tw, tw, t);
+    return tw_source<N, S_ + 1>(i);
   }
 }
 
+// All of a thread's table entries are loaded before any is stored, so that a workgroup waits for
+// one round trip to memory instead of one per stage.
 template <int N, int T, typename V>
 __device__ __forceinline__ void load_stage_twiddles(V* __restrict__ s_tw, const V* __restrict__ tw, int t) {
-  fill_stage_twiddles<N, T, 1>(s_tw, tw, t);
+  constexpr int E = tw_elems(N);
+  constexpr int K = (E + T - 1) / T;
+  V v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t + k * T;
+    v[k] = tw[i < E ? tw_source<N, 1>(i) : 0];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t + k * T;
+    if (i < E) s_tw[i] = v[k];
+  }
   __syncthreads();
 }
 

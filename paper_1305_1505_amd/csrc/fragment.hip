@@ -29,8 +29,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
-#include <stdexcept>
-#include <string>
+#include <vector>
 
 #include "host_math.hpp"
 #include "plan.hpp"
