@@ -218,6 +218,16 @@ void pin_fragment_default_params(pin_fragment_params* out);
 pin_status pin_plan_fragment_workspace_bytes(const pin_plan_desc* desc, size_t* bytes);
 pin_status pin_fragment(pin_plan plan, const void* F, const void* vmax, double f_min, const pin_fragment_params* params,
                         int32_t* label, int32_t* halo_size, int* n_halos, hipStream_t stream);
+/* Halo catalogue of the last pin_fragment call on this plan (section "Fragmentation": halos are
+ * output with their masses, Lagrangian centres of mass and Zel'dovich displacements).  For each
+ * halo in increasing id: id[k], its particle count n_particles[k], its Lagrangian centre of mass
+ * centre[a*capacity + k] (founder position plus the mean minimum-image offset of the members from
+ * it, wrapped into [0, box), Mpc/h) and the mean of its members' vmax, displacement[a*capacity + k]
+ * (Mpc/h at D = 1; times D at the output time for positions).  Device arrays (int32, int32, float64
+ * [3][capacity], float64 [3][capacity]); capacity >= the n_halos of that call.  PIN_ERR_INVALID_ARG
+ * without a completed pin_fragment.  Synchronous. */
+pin_status pin_fragment_catalog(pin_plan plan, int32_t* id, int32_t* n_particles, double* centre, double* displacement,
+                                int capacity, hipStream_t stream);
 
 /* eq. F per point: the inverse collapse time of the ellipsoidal collapse model (the per-point
  * step of pin_collapse_times) for caller-given tensors.  T6 (device, [6][count] of the plan's

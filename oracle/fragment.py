@@ -38,6 +38,10 @@ Readings (the paper leaves these open or garbled):
 * a halo's id is the linear index of the particle that founded it.
 
 Output per particle: NOT_COLLAPSED (-2), FILAMENT (-1), or the id of its halo; and N_h per halo.
+The catalogue (the halo output the section describes: masses, Lagrangian centres of mass, Zel'dovich
+displacements) lists, per halo in increasing id, N_h, the centre of mass q_founder + offsets/N_h
+wrapped into [0, N) and times the cell size (Mpc/h), and the mean displacement u_sum/N_h times the
+cell size (Mpc/h at D = 1).
 """
 
 import numpy as np
@@ -81,11 +85,13 @@ def _wrap(d, n):
     return d - n * np.floor(d / n + 0.5)
 
 
-def fragment(F, u, f_min, n, sigma, params=TABLE1):
+def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None):
     """Sequential fragmentation.
 
     F: (N^3,) inverse collapse times; u: (3, N^3) displacements in grid units at D = 1;
-    sigma: callable R -> sigma(R) at D = 1.  Returns (label (N^3,) int64, nh dict id -> N_h).
+    sigma: callable R -> sigma(R) at D = 1.  Returns (label (N^3,) int64, nh dict id -> N_h), and
+    with catalog_cell (the cell size in Mpc/h) also the catalogue: (ids, N_h, centre (3, H),
+    displacement (3, H)) in increasing id.
     """
     F = np.asarray(F, dtype=np.float64).ravel()
     u = np.asarray(u, dtype=np.float64).reshape(3, -1)
@@ -192,4 +198,14 @@ def fragment(F, u, f_min, n, sigma, params=TABLE1):
     for j in np.nonzero(label >= 0)[0]:
         label[j] = find(int(label[j]))
     sizes = {h: nh[h] for h in parent if parent[h] == h}
-    return label, sizes
+    if catalog_cell is None:
+        return label, sizes
+    ids = np.array(sorted(sizes), dtype=np.int64)
+    cnt = np.array([nh[h] for h in ids], dtype=np.int64)
+    centre = np.zeros((3, len(ids)))
+    disp = np.zeros((3, len(ids)))
+    for k, h in enumerate(ids):
+        c = coords(h) + sq[h] / nh[h]
+        centre[:, k] = (c - n * np.floor(c / n)) * catalog_cell
+        disp[:, k] = su[h] / nh[h] * catalog_cell
+    return label, sizes, (ids, cnt, centre, disp)

@@ -86,6 +86,7 @@ _sig = {
     "pin_plan_fragment_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
     "pin_fragment": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(pin_fragment_params), _vp, _vp,
                                     ctypes.POINTER(ctypes.c_int), _vp]),
+    "pin_fragment_catalog": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
     "pin_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -224,6 +225,11 @@ def pin_plan_fragment_workspace_bytes(desc):
     out = ctypes.c_size_t()
     _check(lib.pin_plan_fragment_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
     return out.value
+
+
+def pin_fragment_catalog(plan, ids, n_particles, centre, displacement, capacity, stream=0):
+    _check(lib.pin_fragment_catalog(plan, _vp(ids), _vp(n_particles), _vp(centre), _vp(displacement), int(capacity),
+                                    _vp(stream)))
 
 
 def pin_fragment(plan, F, vmax, f_min, params, label, halo_size, stream=0):
@@ -389,6 +395,19 @@ class Plan:
         count = pin_fragment(self.handle, F.data_ptr(), vmax.data_ptr(), f_min, params, label.data_ptr(),
                              sizes.data_ptr() if sizes is not None else 0, self._stream())
         return label, sizes, count
+
+    def fragment_catalog(self, n_halos):
+        """(ids, n_particles, centre [3, H], displacement [3, H]) of the last fragment() -- pin_fragment_catalog."""
+        t = self.torch
+        h = max(int(n_halos), 1)
+        ids = t.empty(h, dtype=t.int32, device="cuda")
+        cnt = t.empty(h, dtype=t.int32, device="cuda")
+        centre = t.empty((3, h), dtype=t.float64, device="cuda")
+        disp = t.empty((3, h), dtype=t.float64, device="cuda")
+        pin_fragment_catalog(self.handle, ids.data_ptr(), cnt.data_ptr(), centre.data_ptr(), disp.data_ptr(), h,
+                             self._stream())
+        k = int(n_halos)
+        return ids[:k], cnt[:k], centre[:, :k], disp[:, :k]
 
     def lpt3_displacement(self, dk):
         """psi3 (3, N, N, N) at D = 1 in Mpc/h (pin_lpt3_displacement)."""

@@ -257,6 +257,21 @@ pin_status pin_fragment(pin_plan plan, const void* F, const void* vmax, double f
   });
 }
 
+pin_status pin_fragment_catalog(pin_plan plan, int32_t* id, int32_t* n_particles, double* centre, double* displacement,
+                                int capacity, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (plan->frag.n_halos < 0) fail(PIN_ERR_INVALID_ARG, "no fragmentation result on this plan");
+    if (capacity < plan->frag.n_halos) fail(PIN_ERR_INVALID_ARG, "capacity is smaller than the number of halos");
+    const size_t cap = capacity > 0 ? (size_t)capacity : 1;
+    check_device_range(id, cap * sizeof(int32_t), "id");
+    check_device_range(n_particles, cap * sizeof(int32_t), "n_particles");
+    check_device_range(centre, 3 * cap * sizeof(double), "centre");
+    check_device_range(displacement, 3 * cap * sizeof(double), "displacement");
+    fragment_catalog(plan->frag, plan->box / plan->n, id, n_particles, centre, displacement, capacity, stream);
+  });
+}
+
 pin_status pin_plan_lpt3_workspace_bytes(const pin_plan_desc* desc, size_t* bytes) {
   return guarded([&] {
     validate_desc(desc);

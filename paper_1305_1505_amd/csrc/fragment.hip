@@ -406,14 +406,45 @@ __global__ void __launch_bounds__(1024) k_sum(const int32_t* __restrict__ in, in
   if (threadIdx.x == 0) *out = (int32_t)part[0];
 }
 
+// Catalogue: flags of the halo roots, then one entry per selected id.
+__global__ void k_root_flags(const int32_t* __restrict__ parent, const int32_t* __restrict__ hn, size_t vol,
+                             uint8_t* __restrict__ flags) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vol) return;
+  flags[i] = parent[i] == (int32_t)i && hn[i] > 0;
+}
+
+__global__ void k_catalog(const int32_t* __restrict__ id, const int32_t* __restrict__ count, int n, size_t vol,
+                          const int32_t* __restrict__ hn, const double* __restrict__ hs, double cell, int capacity,
+                          int32_t* __restrict__ nh_out, double* __restrict__ centre, double* __restrict__ disp) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *count || k >= capacity) return;
+  const int h = id[k];
+  const double nd = (double)n;
+  const double nh = (double)hn[h];
+  const double q[3] = {(double)(h / (n * n)), (double)((h / n) % n), (double)(h % n)};
+  nh_out[k] = hn[h];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double c = q[a] + hs[(size_t)a * vol + h] / nh;
+    centre[(size_t)a * capacity + k] = (c - nd * floor(c / nd)) * cell;
+    disp[(size_t)a * capacity + k] = hs[(size_t)(3 + a) * vol + h] / nh * cell;
+  }
+}
+
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// Temporary storage of the radix sort and of the catalogue's selection (one buffer for both).
 size_t sort_tmp_bytes(size_t vol) {
-  size_t tmp = 0;
+  size_t tmp = 0, sel = 0;
   hipcub::DoubleBuffer<uint64_t> kb(nullptr, nullptr);
   hipcub::DoubleBuffer<int32_t> vb(nullptr, nullptr);
   hip_check(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)vol, 0, 64), "radix sort size");
-  return tmp;
+  hip_check(hipcub::DeviceSelect::Flagged(nullptr, sel, hipcub::CountingInputIterator<int32_t>(0),
+                                          static_cast<const uint8_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                                          static_cast<int32_t*>(nullptr), (int)vol),
+            "select size");
+  return tmp > sel ? tmp : sel;
 }
 
 }  // namespace
@@ -491,6 +522,7 @@ int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* 
   const size_t vol = (size_t)n * n * n;
   const int block = 256;
   const int grid = (int)((vol + block - 1) / block);
+  w.n_halos = -1;   // no catalogue until this run completes
   hip_check(hipMemsetAsync(w.ctl, 0, 64, s), "hipMemsetAsync");
   if (fp64) {
     hipLaunchKernelGGL(k_keys<double>, dim3(grid), dim3(block), 0, s, static_cast<const double*>(F), vol, f_min,
@@ -571,7 +603,33 @@ int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* 
   hip_check(hipGetLastError(), "fragmentation finish");
   hip_check(hipMemcpyAsync(w.host_ctl, w.ctl, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-  return w.host_ctl[4];
+  w.n_halos = w.host_ctl[4];
+  w.n = n;
+  return w.n_halos;
+}
+
+int fragment_catalog(FragWorkspace& w, double cell, int32_t* id, int32_t* nh, double* centre, double* disp,
+                     int capacity, hipStream_t s) {
+  const size_t vol = w.vol;
+  const int block = 256;
+  const int grid = (int)((vol + block - 1) / block);
+  uint8_t* flags = reinterpret_cast<uint8_t*>(w.keys[1]);
+  hipLaunchKernelGGL(k_root_flags, dim3(grid), dim3(block), 0, s, w.parent, w.hn, vol, flags);
+  hip_check(hipGetLastError(), "catalogue flags");
+  size_t tmp = w.sort_tmp_bytes;
+  hip_check(hipcub::DeviceSelect::Flagged(w.sort_tmp, tmp, hipcub::CountingInputIterator<int32_t>(0), flags, id,
+                                          w.ctl + 5, (int)vol, s),
+            "catalogue select");
+  const int cgrid = (w.n_halos + block - 1) / block;
+  if (cgrid > 0) {
+    hipLaunchKernelGGL(k_catalog, dim3(cgrid), dim3(block), 0, s, id, w.ctl + 5, w.n, vol, w.hn, w.hs, cell, capacity,
+                       nh, centre, disp);
+    hip_check(hipGetLastError(), "catalogue");
+  }
+  hip_check(hipMemcpyAsync(w.host_ctl, w.ctl, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (w.host_ctl[5] != w.n_halos) fail(PIN_ERR_DEVICE, "catalogue: halo count differs from the fragmentation's");
+  return w.n_halos;
 }
 
 }  // namespace pin

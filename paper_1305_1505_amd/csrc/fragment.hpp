@@ -36,6 +36,8 @@ struct FragWorkspace {
   int stab_n = 0;
   double s_r0 = 0, s_step = 0;
   int32_t* host_ctl = nullptr;    // pinned mirror of ctl
+  int n_halos = -1;               // halos of the last fragment_run (-1: none yet)
+  int n = 0;                      // its grid size
 };
 
 // Bytes of the workspace for an N^3 grid.
@@ -52,5 +54,11 @@ void fragment_free(FragWorkspace& w);
 // the number of halos.  Synchronous: the rounds are driven from the host.
 int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* v, double uscale, double f_min,
                  const FragParams& prm, int32_t* label, int32_t* halo_size, hipStream_t s);
+
+// Catalogue of the last fragment_run: for each halo in increasing id, its id, N_h, Lagrangian
+// centre of mass (founder + mean offset, wrapped into [0, N), times cell) and mean displacement
+// (times cell), centre and disp [3][capacity] float64.  Synchronous; returns the halo count.
+int fragment_catalog(FragWorkspace& w, double cell, int32_t* id, int32_t* nh, double* centre, double* disp,
+                     int capacity, hipStream_t s);
 
 }  // namespace pin

@@ -40,13 +40,22 @@ def _run_both(lib, n, box, seed, prec, f_min, n_radii=12):
     tF = torch.from_numpy(Fq.reshape(n, n, n)).cuda()
     tv = torch.from_numpy(vq.reshape(3, n, n, n)).cuda()
     label, sizes, count = plan.fragment(tF, tv, f_min)
+    cat = [t.cpu().numpy() for t in plan.fragment_catalog(count)]
     torch.cuda.synchronize()
     label, sizes = label.cpu().numpy().ravel(), sizes.cpu().numpy().ravel()
     plan.close()
     print(f"[fragment] n={n} f_min={f_min}: {count} halos, {int(np.sum(label == -1))} filament, "
           f"{int(np.sum(label >= 0))} in halos", flush=True)
     sigma = FR.SigmaTable(n, box, W.SIGMA8, W.GAMMA, W.NS, nh_max=n ** 3)
-    ref, ref_sizes = FR.fragment(Fq.astype(np.float64), vq.astype(np.float64) * (n / box), f_min, n, sigma)
+    ref, ref_sizes, ref_cat = FR.fragment(Fq.astype(np.float64), vq.astype(np.float64) * (n / box), f_min, n, sigma,
+                                          catalog_cell=box / n)
+    # catalogue: same ids and counts; centres and displacements from sums accumulated in the same
+    # order with the same operations
+    assert np.array_equal(cat[0], ref_cat[0]) and np.array_equal(cat[1], ref_cat[1])
+    dc = np.max(np.abs(cat[2] - ref_cat[2])) if count else 0.0
+    dd = np.max(np.abs(cat[3] - ref_cat[3])) if count else 0.0
+    print(f"[fragment] catalogue: max |d centre| {dc:.3g}, max |d displacement| {dd:.3g} Mpc/h", flush=True)
+    assert dc <= 1e-12 * box and dd <= 1e-12 * box
     return label, sizes, count, ref, ref_sizes
 
 
@@ -126,6 +135,9 @@ def test_fragment_argument_errors(lib):
         with pytest.raises(lib.PinError) as e:
             lib.pin_fragment(plan.handle, args[0], args[1], 1.0, None, args[2], 0)
         assert e.value.status == lib.PIN_ERR_INVALID_ARG
+    with pytest.raises(lib.PinError) as e:          # no fragmentation on this plan yet
+        plan.fragment_catalog(4)
+    assert e.value.status == lib.PIN_ERR_INVALID_ARG
     bad = lib.pin_fragment_default_params()
     bad.f_m = float("nan")
     with pytest.raises(lib.PinError):

@@ -55,6 +55,26 @@ def test_converging_sphere_is_one_halo():
     assert sizes[h] == int(np.sum(collapsed))
 
 
+def test_catalogue_of_a_converging_sphere():
+    """One halo: its Lagrangian centre of mass is the peak (the members are symmetric about it) and
+    its mean displacement vanishes (u is odd about the peak)."""
+    F, u = sphere((8, 8, 8))
+    label, sizes, (ids, cnt, centre, disp) = FR.fragment(F, u, 1.0, N, flat_sigma, catalog_cell=2.0)
+    assert list(ids) == [8 * N * N + 8 * N + 8] and int(cnt[0]) == int(np.sum(F >= 1.0))
+    assert np.allclose(centre[:, 0], 16.0, rtol=0, atol=1e-12)
+    assert np.allclose(disp[:, 0], 0.0, rtol=0, atol=1e-12)
+
+
+def test_catalogue_wraps_into_the_box():
+    """A converging sphere centred on a corner: members on both sides of the periodic boundary, the
+    centre of mass at the corner (0 after wrapping, not N/2)."""
+    F, u = sphere((0, 0, 0))
+    _, _, (ids, cnt, centre, _) = FR.fragment(F, u, 1.0, N, flat_sigma, catalog_cell=1.0)
+    assert len(ids) == 1
+    c = np.minimum(centre[:, 0], N - centre[:, 0])
+    assert np.all(c <= 1e-12)
+
+
 def test_diverging_sphere_is_a_peak_and_filaments():
     F, u = sphere((8, 8, 8), sign=+1.0)
     label, sizes = FR.fragment(F, u, 1.0, N, flat_sigma)
