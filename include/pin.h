@@ -228,6 +228,15 @@ pin_status pin_fragment(pin_plan plan, const void* F, const void* vmax, double f
  * without a completed pin_fragment.  Synchronous. */
 pin_status pin_fragment_catalog(pin_plan plan, int32_t* id, int32_t* n_particles, double* centre, double* displacement,
                                 int capacity, hipStream_t stream);
+/* Merger history of the last pin_fragment call on this plan (section "Fragmentation": reported at
+ * the final time, the masses of the merging halos at each merger), in the order the mergers
+ * happened: f[k] the F_max of the particle whose step merged the halos (D = 1/f), keep[k] the id
+ * of the halo that keeps its id and n_keep[k] its particle count before the merger, gone[k] and
+ * n_gone[k] those of the halo absorbed.  Device arrays of `capacity` entries (float64, int32 x 4);
+ * *count (host) receives the number of mergers.  With capacity 0 and every array NULL the call
+ * only sets *count; otherwise capacity below the count is PIN_ERR_INVALID_ARG.  Synchronous. */
+pin_status pin_fragment_mergers(pin_plan plan, double* f, int32_t* keep, int32_t* gone, int32_t* n_keep,
+                                int32_t* n_gone, int capacity, int* count, hipStream_t stream);
 
 /* eq. F per point: the inverse collapse time of the ellipsoidal collapse model (the per-point
  * step of pin_collapse_times) for caller-given tensors.  T6 (device, [6][count] of the plan's

@@ -41,7 +41,9 @@ Output per particle: NOT_COLLAPSED (-2), FILAMENT (-1), or the id of its halo; a
 The catalogue (the halo output the section describes: masses, Lagrangian centres of mass, Zel'dovich
 displacements) lists, per halo in increasing id, N_h, the centre of mass q_founder + offsets/N_h
 wrapped into [0, N) and times the cell size (Mpc/h), and the mean displacement u_sum/N_h times the
-cell size (Mpc/h at D = 1).
+cell size (Mpc/h at D = 1).  The merger history (reported at the final time: the masses of the
+merging halos at each merger) lists every merger in the order it happened: the F_max of the particle
+whose step caused it, the id and N_h of the halo that keeps its id, and those of the one absorbed.
 """
 
 import numpy as np
@@ -85,13 +87,14 @@ def _wrap(d, n):
     return d - n * np.floor(d / n + 0.5)
 
 
-def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None):
+def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None, want_mergers=False):
     """Sequential fragmentation.
 
     F: (N^3,) inverse collapse times; u: (3, N^3) displacements in grid units at D = 1;
     sigma: callable R -> sigma(R) at D = 1.  Returns (label (N^3,) int64, nh dict id -> N_h), and
     with catalog_cell (the cell size in Mpc/h) also the catalogue: (ids, N_h, centre (3, H),
-    displacement (3, H)) in increasing id.
+    displacement (3, H)) in increasing id, and with want_mergers the merger list
+    [(F, keep, gone, N_keep before, N_gone)] in the order the mergers happened (appended last).
     """
     F = np.asarray(F, dtype=np.float64).ravel()
     u = np.asarray(u, dtype=np.float64).reshape(3, -1)
@@ -100,6 +103,7 @@ def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None):
     label = np.full(vol, NOT_COLLAPSED, dtype=np.int64)
     parent = {}
     nh, sq, su = {}, {}, {}
+    mergers = []
 
     idx = np.nonzero(F >= f_min)[0]
     order = idx[np.lexsort((idx, -F[idx]))]       # F descending, then index ascending
@@ -182,6 +186,7 @@ def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None):
                     dab = dist(position(ha, D), position(hb, D))
                     if dab < fm * max(halo_radius(nh[ha]), halo_radius(nh[hb])) + frm:
                         keep, gone = (ha, hb) if (nh[ha], -ha) >= (nh[hb], -hb) else (hb, ha)
+                        mergers.append((F[i], keep, gone, nh[keep], nh[gone]))
                         off = _wrap(coords(gone) - coords(keep), n)
                         sq[keep] = sq[keep] + sq[gone] + nh[gone] * off
                         su[keep] = su[keep] + su[gone]
@@ -198,8 +203,11 @@ def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None):
     for j in np.nonzero(label >= 0)[0]:
         label[j] = find(int(label[j]))
     sizes = {h: nh[h] for h in parent if parent[h] == h}
+    extra = ()
+    if want_mergers:
+        extra = (mergers,)
     if catalog_cell is None:
-        return label, sizes
+        return (label, sizes) + extra
     ids = np.array(sorted(sizes), dtype=np.int64)
     cnt = np.array([nh[h] for h in ids], dtype=np.int64)
     centre = np.zeros((3, len(ids)))
@@ -208,4 +216,4 @@ def fragment(F, u, f_min, n, sigma, params=TABLE1, catalog_cell=None):
         c = coords(h) + sq[h] / nh[h]
         centre[:, k] = (c - n * np.floor(c / n)) * catalog_cell
         disp[:, k] = su[h] / nh[h] * catalog_cell
-    return label, sizes, (ids, cnt, centre, disp)
+    return (label, sizes, (ids, cnt, centre, disp)) + extra

@@ -87,6 +87,7 @@ _sig = {
     "pin_fragment": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(pin_fragment_params), _vp, _vp,
                                     ctypes.POINTER(ctypes.c_int), _vp]),
     "pin_fragment_catalog": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "pin_fragment_mergers": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _vp]),
     "pin_inverse_collapse_time": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "pin_kernel_class_count": (ctypes.c_int, []),
     "pin_kernel_class_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -230,6 +231,14 @@ def pin_plan_fragment_workspace_bytes(desc):
 def pin_fragment_catalog(plan, ids, n_particles, centre, displacement, capacity, stream=0):
     _check(lib.pin_fragment_catalog(plan, _vp(ids), _vp(n_particles), _vp(centre), _vp(displacement), int(capacity),
                                     _vp(stream)))
+
+
+def pin_fragment_mergers(plan, f, keep, gone, n_keep, n_gone, capacity, stream=0):
+    """Returns the number of mergers (with capacity 0 and all arrays 0: only the count)."""
+    c = ctypes.c_int(0)
+    _check(lib.pin_fragment_mergers(plan, _vp(f or None), _vp(keep or None), _vp(gone or None), _vp(n_keep or None),
+                                    _vp(n_gone or None), int(capacity), ctypes.byref(c), _vp(stream)))
+    return c.value
 
 
 def pin_fragment(plan, F, vmax, f_min, params, label, halo_size, stream=0):
@@ -408,6 +417,16 @@ class Plan:
                              self._stream())
         k = int(n_halos)
         return ids[:k], cnt[:k], centre[:, :k], disp[:, :k]
+
+    def fragment_mergers(self):
+        """(f, keep, gone, n_keep, n_gone) of the last fragment(), in the order the mergers happened."""
+        t = self.torch
+        m = pin_fragment_mergers(self.handle, 0, 0, 0, 0, 0, 0, self._stream())
+        h = max(m, 1)
+        f = t.empty(h, dtype=t.float64, device="cuda")
+        ints = [t.empty(h, dtype=t.int32, device="cuda") for _ in range(4)]
+        pin_fragment_mergers(self.handle, f.data_ptr(), *[x.data_ptr() for x in ints], h, self._stream())
+        return (f[:m],) + tuple(x[:m] for x in ints)
 
     def lpt3_displacement(self, dk):
         """psi3 (3, N, N, N) at D = 1 in Mpc/h (pin_lpt3_displacement)."""

@@ -272,6 +272,29 @@ pin_status pin_fragment_catalog(pin_plan plan, int32_t* id, int32_t* n_particles
   });
 }
 
+pin_status pin_fragment_mergers(pin_plan plan, double* f, int32_t* keep, int32_t* gone, int32_t* n_keep,
+                                int32_t* n_gone, int capacity, int* count, hipStream_t stream) {
+  return guarded([&] {
+    check_plan(plan);
+    if (count == nullptr) fail(PIN_ERR_INVALID_ARG, "count is NULL");
+    if (plan->frag.n_halos < 0) fail(PIN_ERR_INVALID_ARG, "no fragmentation result on this plan");
+    const int m = plan->frag.n_mergers;
+    if (capacity == 0 && f == nullptr && keep == nullptr && gone == nullptr && n_keep == nullptr && n_gone == nullptr) {
+      *count = m;   // query
+      return;
+    }
+    if (capacity < m) fail(PIN_ERR_INVALID_ARG, "capacity is smaller than the number of mergers");
+    if (m > 0) {
+      check_device_range(f, (size_t)m * sizeof(double), "f");
+      check_device_range(keep, (size_t)m * sizeof(int32_t), "keep");
+      check_device_range(gone, (size_t)m * sizeof(int32_t), "gone");
+      check_device_range(n_keep, (size_t)m * sizeof(int32_t), "n_keep");
+      check_device_range(n_gone, (size_t)m * sizeof(int32_t), "n_gone");
+    }
+    *count = fragment_mergers(plan->frag, f, keep, gone, n_keep, n_gone, capacity, stream);
+  });
+}
+
 pin_status pin_plan_lpt3_workspace_bytes(const pin_plan_desc* desc, size_t* bytes) {
   return guarded([&] {
     validate_desc(desc);

@@ -68,6 +68,9 @@ struct Dev {
   double s_r0, s_step;
   double uscale;
   FragParams prm;
+  unsigned long long* ev_key;
+  double* ev_f;
+  int32_t* ev_ids;
 };
 
 __device__ __forceinline__ void neighbours(int i, int n, int (&nb)[6]) {
@@ -235,7 +238,7 @@ __device__ __forceinline__ void load_u(const R* v, size_t vol, int j, double usc
 }
 
 template <typename R>
-__device__ void execute(const Dev& d, const R* F, const R* v, int i, const int (&nb)[6], const int (&halos)[6],
+__device__ void execute(const Dev& d, const R* F, const R* v, int p, int i, const int (&nb)[6], const int (&halos)[6],
                         int hc) {
   const Step st{d, 1.0 / (double)F[i]};
   double q[3], ui[3], xi[3];
@@ -310,6 +313,18 @@ __device__ void execute(const Dev& d, const R* F, const R* v, int i, const int (
         if (dab < d.prm.fm * (ra > rb ? ra : rb) + d.prm.frm) {
           const bool keep_a = d.hn[ha] > d.hn[hb] || (d.hn[ha] == d.hn[hb] && ha <= hb);
           const int keep = keep_a ? ha : hb, gone = keep_a ? hb : ha;
+          // merger event, tagged with its place in the sequential order (particle, pair)
+          const int e = atomicAdd(&d.ctl[6], 1);
+          if (e < (int)d.vol) {
+            d.ev_key[e] = ((unsigned long long)p << 8) | (unsigned)(a * 8 + b);
+            d.ev_f[e] = (double)F[i];
+            d.ev_ids[4 * (size_t)e + 0] = keep;
+            d.ev_ids[4 * (size_t)e + 1] = gone;
+            d.ev_ids[4 * (size_t)e + 2] = d.hn[keep];
+            d.ev_ids[4 * (size_t)e + 3] = d.hn[gone];
+          } else {
+            d.ctl[7] = 1;
+          }
           double qk[3], qg[3];
           st.coords(keep, qk);
           st.coords(gone, qg);
@@ -365,7 +380,7 @@ __global__ void k_commit(Dev d, unsigned long long hi, const R* __restrict__ F, 
     atomicMin(&d.ctl[1], p);
     return;
   }
-  execute<R>(d, F, v, i, nb, halos, hc);
+  execute<R>(d, F, v, p, i, nb, halos, hc);
 }
 
 __global__ void k_advance(int32_t* ctl, int m, int window) {
@@ -432,6 +447,24 @@ __global__ void k_catalog(const int32_t* __restrict__ id, const int32_t* __restr
   }
 }
 
+__global__ void k_iota(int32_t* __restrict__ x, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[i] = i;
+}
+
+__global__ void k_gather_mergers(const int32_t* __restrict__ idx, int count, const double* __restrict__ ev_f,
+                                 const int32_t* __restrict__ ev_ids, double* __restrict__ f, int32_t* __restrict__ keep,
+                                 int32_t* __restrict__ gone, int32_t* __restrict__ n_keep, int32_t* __restrict__ n_gone) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const int e = idx[k];
+  f[k] = ev_f[e];
+  keep[k] = ev_ids[4 * (size_t)e + 0];
+  gone[k] = ev_ids[4 * (size_t)e + 1];
+  n_keep[k] = ev_ids[4 * (size_t)e + 2];
+  n_gone[k] = ev_ids[4 * (size_t)e + 3];
+}
+
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Temporary storage of the radix sort and of the catalogue's selection (one buffer for both).
@@ -457,6 +490,7 @@ size_t fragment_workspace_bytes(int n) {
   b += 2 * align256(vol * 4) + align256(vol * 6 * 8);   // parent, hn, hs
   b += 2 * align256(vol * 8);                           // reservations
   b += align256((size_t)kWindow * 7 * 4) + 256;      // items, ctl
+  b += 2 * align256(vol * 8) + align256(vol * 16);      // merger events
   b += align256((size_t)kRadiusTable * 8);
   b += align256(64 * 40 * 8);                           // sigma nodes (<= 40 octaves)
   return b;
@@ -495,6 +529,9 @@ void fragment_prepare(FragWorkspace& w, int n, double box, double amplitude, dou
     w.res_halo = reinterpret_cast<unsigned long long*>(take(vol * 8));
     w.items = reinterpret_cast<int32_t*>(take((size_t)kWindow * 7 * 4));
     w.ctl = reinterpret_cast<int32_t*>(take(256));
+    w.ev_key = reinterpret_cast<unsigned long long*>(take(vol * 8));
+    w.ev_f = reinterpret_cast<double*>(take(vol * 8));
+    w.ev_ids = reinterpret_cast<int32_t*>(take(vol * 16));
     w.rtab = reinterpret_cast<double*>(take((size_t)kRadiusTable * 8));
     w.stab = reinterpret_cast<double*>(take(64 * 40 * 8));
     void* hc = nullptr;
@@ -565,6 +602,9 @@ int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* 
   d.s_step = w.s_step;
   d.uscale = uscale;
   d.prm = prm;
+  d.ev_key = w.ev_key;
+  d.ev_f = w.ev_f;
+  d.ev_ids = w.ev_ids;
   const int window = kWindow;
   d.window = window;
   // head = 0, next head = end of the first window
@@ -603,9 +643,31 @@ int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* 
   hip_check(hipGetLastError(), "fragmentation finish");
   hip_check(hipMemcpyAsync(w.host_ctl, w.ctl, 32, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (w.host_ctl[7] != 0) fail(PIN_ERR_DEVICE, "fragmentation: merger events exceed the grid size");
   w.n_halos = w.host_ctl[4];
+  w.n_mergers = w.host_ctl[6];
   w.n = n;
   return w.n_halos;
+}
+
+int fragment_mergers(FragWorkspace& w, double* f, int32_t* keep, int32_t* gone, int32_t* n_keep, int32_t* n_gone,
+                     int capacity, hipStream_t s) {
+  const int count = w.n_mergers;
+  if (count == 0) return 0;
+  const int block = 256;
+  const int grid = (count + block - 1) / block;
+  // sort copies of the keys (the events stay as recorded, so the call can be repeated)
+  hip_check(hipMemcpyAsync(w.keys[0], w.ev_key, (size_t)count * 8, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+  hipLaunchKernelGGL(k_iota, dim3(grid), dim3(block), 0, s, w.vals[0], count);
+  hipcub::DoubleBuffer<uint64_t> kb(w.keys[0], w.keys[1]);
+  hipcub::DoubleBuffer<int32_t> vb(w.vals[0], w.vals[1]);
+  size_t tmp = w.sort_tmp_bytes;
+  hip_check(hipcub::DeviceRadixSort::SortPairs(w.sort_tmp, tmp, kb, vb, count, 0, 40, s), "merger sort");
+  hipLaunchKernelGGL(k_gather_mergers, dim3(grid), dim3(block), 0, s, vb.Current(), count < capacity ? count : capacity,
+                     w.ev_f, w.ev_ids, f, keep, gone, n_keep, n_gone);
+  hip_check(hipGetLastError(), "merger gather");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return count;
 }
 
 int fragment_catalog(FragWorkspace& w, double cell, int32_t* id, int32_t* nh, double* centre, double* disp,

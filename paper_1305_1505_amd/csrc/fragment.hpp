@@ -30,13 +30,17 @@ struct FragWorkspace {
   unsigned long long* res_cell = nullptr;
   unsigned long long* res_halo = nullptr;
   int32_t* items = nullptr;       // per window slot: count + up to 6 halo ids
-  int32_t* ctl = nullptr;         // head, next head, error, participant count
+  int32_t* ctl = nullptr;         // head, next head, error, participants, halos, selected, mergers, overflow
+  unsigned long long* ev_key = nullptr;  // merger events: (order position << 8 | pair), capacity vol
+  double* ev_f = nullptr;                // F of the particle whose step merged
+  int32_t* ev_ids = nullptr;             // keep, gone, N_keep before, N_gone
   double* rtab = nullptr;         // halo radius for N_h = 1..kRadiusTable
   double* stab = nullptr;         // sigma(R) nodes
   int stab_n = 0;
   double s_r0 = 0, s_step = 0;
   int32_t* host_ctl = nullptr;    // pinned mirror of ctl
   int n_halos = -1;               // halos of the last fragment_run (-1: none yet)
+  int n_mergers = 0;              // its merger events
   int n = 0;                      // its grid size
 };
 
@@ -59,6 +63,12 @@ int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* 
 // centre of mass (founder + mean offset, wrapped into [0, N), times cell) and mean displacement
 // (times cell), centre and disp [3][capacity] float64.  Synchronous; returns the halo count.
 int fragment_catalog(FragWorkspace& w, double cell, int32_t* id, int32_t* nh, double* centre, double* disp,
+                     int capacity, hipStream_t s);
+
+// Merger history of the last fragment_run, in the order the mergers happened: F of the particle
+// that caused each, the kept and the absorbed halo ids and their N_h before the merger.  Device
+// outputs of `capacity` entries; synchronous; returns the number of mergers.
+int fragment_mergers(FragWorkspace& w, double* f, int32_t* keep, int32_t* gone, int32_t* n_keep, int32_t* n_gone,
                      int capacity, hipStream_t s);
 
 }  // namespace pin

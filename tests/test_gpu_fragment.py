@@ -41,14 +41,23 @@ def _run_both(lib, n, box, seed, prec, f_min, n_radii=12):
     tv = torch.from_numpy(vq.reshape(3, n, n, n)).cuda()
     label, sizes, count = plan.fragment(tF, tv, f_min)
     cat = [t.cpu().numpy() for t in plan.fragment_catalog(count)]
+    mer = [t.cpu().numpy() for t in plan.fragment_mergers()]
     torch.cuda.synchronize()
     label, sizes = label.cpu().numpy().ravel(), sizes.cpu().numpy().ravel()
     plan.close()
     print(f"[fragment] n={n} f_min={f_min}: {count} halos, {int(np.sum(label == -1))} filament, "
           f"{int(np.sum(label >= 0))} in halos", flush=True)
     sigma = FR.SigmaTable(n, box, W.SIGMA8, W.GAMMA, W.NS, nh_max=n ** 3)
-    ref, ref_sizes, ref_cat = FR.fragment(Fq.astype(np.float64), vq.astype(np.float64) * (n / box), f_min, n, sigma,
-                                          catalog_cell=box / n)
+    ref, ref_sizes, ref_cat, ref_mer = FR.fragment(Fq.astype(np.float64), vq.astype(np.float64) * (n / box), f_min, n,
+                                                   sigma, catalog_cell=box / n, want_mergers=True)
+    # merger history: the same events in the same order
+    print(f"[fragment] {len(ref_mer)} mergers", flush=True)
+    assert len(mer[0]) == len(ref_mer)
+    if ref_mer:
+        rm = np.array(ref_mer)
+        assert np.array_equal(mer[0], rm[:, 0])
+        for c in range(4):
+            assert np.array_equal(mer[1 + c], rm[:, 1 + c].astype(np.int64))
     # catalogue: same ids and counts; centres and displacements from sums accumulated in the same
     # order with the same operations
     assert np.array_equal(cat[0], ref_cat[0]) and np.array_equal(cat[1], ref_cat[1])

@@ -75,6 +75,34 @@ def test_catalogue_wraps_into_the_box():
     assert np.all(c <= 1e-12)
 
 
+def test_merger_history_of_two_converging_peaks():
+    """The two-peak case merges exactly once: the first halo (the higher peak founds it) keeps its
+    id unless the other has grown larger, the sizes add up to the final halo, and the merger
+    happens at the F of a particle touching both halos."""
+    q = grid()
+    c1, c2, mid = np.array([8.0, 6.0, 8.0]), np.array([8.0, 10.0, 8.0]), np.array([8.0, 8.0, 8.0])
+    d1 = min_image(q - c1[:, None])
+    d2 = min_image(q - c2[:, None])
+    F = 2.0 - 0.05 * np.minimum(np.sum(d1 * d1, axis=0), np.sum(d2 * d2, axis=0) + 0.01)
+    u = -min_image(q - mid[:, None]) * F
+    label, sizes, mergers = FR.fragment(F, u, 1.2, N, flat_sigma, want_mergers=True)
+    assert len(mergers) == 1
+    f, keep, gone, nk, ng = mergers[0]
+    assert {keep, gone} == {8 * N * N + 6 * N + 8, 8 * N * N + 10 * N + 8}
+    assert nk >= ng and (nk > ng or keep < gone)
+    assert sizes == {keep: sizes[keep]} and nk + ng <= sizes[keep]
+    assert 1.2 <= f < 2.0
+
+
+def test_no_mergers_for_distant_spheres():
+    F1, u1 = sphere((4, 4, 4), f0=1.5, slope=0.1)
+    F2, u2 = sphere((12, 12, 12), f0=1.4, slope=0.1)
+    take = F1 >= F2
+    _, _, mergers = FR.fragment(np.where(take, F1, F2), np.where(take[None], u1, u2), 1.0, N, flat_sigma,
+                                want_mergers=True)
+    assert mergers == []
+
+
 def test_diverging_sphere_is_a_peak_and_filaments():
     F, u = sphere((8, 8, 8), sign=+1.0)
     label, sizes = FR.fragment(F, u, 1.0, N, flat_sigma)
