@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(cls, n, real_bytes):
-    """Bytes a launch of kernel class `cls` must move at grid size n (see the design doc table)."""
+    """Bytes a launch of kernel class `cls` must move at grid size n: its input and output workspace
+    slots (a slot is one N x N x N/2 complex array) and, for the collapse pass, F and the radius index."""
     cb = 2 * real_bytes
     slot = n * n * (n // 2) * cb          # one workspace slot (kz = N/2 plane not stored)
     vol = n ** 3
@@ -215,8 +216,8 @@ def main():
                     help="also run three plain 1 GiB device copies (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a realization would shard by "
+              "radius with one max-merge of the running state)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -129,6 +129,28 @@ def test_fragment_spheres(lib):
     plan.close()
 
 
+def test_fragment_edge_cases(lib):
+    """No participant (f_min above every F): all labels NOT_COLLAPSED, no halo, empty catalogue and
+    history.  Every F equal: the order is the linear index alone, and the result (ties in the
+    order, in d/R and in sizes everywhere) equals the oracle's."""
+    import torch
+
+    n, box = 16, 16.0
+    plan = lib.Plan(n, box, [1.0], sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=lib.PIN_FP64)
+    F = torch.full((n, n, n), 1.5, dtype=torch.float64, device="cuda")
+    v = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+    label, sizes, count = plan.fragment(F, v, 2.0)
+    assert count == 0 and bool((label == -2).all()) and int(sizes.sum()) == 0
+    assert plan.fragment_catalog(0)[0].numel() == 0 and plan.fragment_mergers()[0].numel() == 0
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((3, n ** 3)) * 0.3
+    label, sizes, count = plan.fragment(F, torch.from_numpy(u.reshape(3, n, n, n)).cuda(), 1.0)
+    sigma = FR.SigmaTable(n, box, W.SIGMA8, W.GAMMA, W.NS, nh_max=n ** 3)
+    ref, ref_sizes = FR.fragment(np.full(n ** 3, 1.5), u * (n / box), 1.0, n, sigma)
+    assert count == len(ref_sizes) and np.array_equal(label.cpu().numpy().ravel(), ref)
+    plan.close()
+
+
 def test_fragment_argument_errors(lib):
     import torch
 
