@@ -78,6 +78,9 @@ struct Strided {
   // each thread owns one butterfly and the transform ends in registers (the x and y passes keep
   // one transform's data live, within 64 VGPRs); otherwise 4 (float64 tiles are LDS-bound there)
   static constexpr int WPE = (sizeof(V) == 8 && E::K0 == 1 && E::SAME && E::max_held() <= E::R0) ? 8 : 4;
+  // the float64 x pass keeps three outputs' multipliers and a transform live: at 4 waves per SIMD
+  // it spills; 2 waves (1.37 -> 1.21 ms at 512^3)
+  static constexpr int XWPE = sizeof(V) == 16 ? 2 : WPE;
   static constexpr int GRID = N * NZT;
   static constexpr size_t HSLOT = (size_t)N * N * HZ;
 };
@@ -165,7 +168,7 @@ __global__ void k_prep(const typename Cplx<R>::type* __restrict__ dk, typename C
 // wait for each one before issuing the next.
 template <typename R, int N, int MODE>
 __global__ void __launch_bounds__((Strided<R, N, +1>::T))
-__attribute__((amdgpu_waves_per_eu(Strided<R, N, +1>::WPE, Strided<R, N, +1>::WPE)))
+__attribute__((amdgpu_waves_per_eu(Strided<R, N, +1>::XWPE, Strided<R, N, +1>::XWPE)))
 k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
         const R* __restrict__ wtab, const typename Cplx<R>::type* __restrict__ tw, R scale) {
   using S = Strided<R, N, +1>;
