@@ -59,24 +59,31 @@ void ypass(int recipe, const void* in, void* out, const void* tw, hipStream_t s)
   if (recipe == 0) {
     using S = Strided<RR, NN, +1>;
     hipLaunchKernelGGL((k_ypass_packed<RR, NN, 0>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
-                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+                       static_cast<VV*>(out), static_cast<const VV*>(tw), static_cast<VV*>(nullptr));
   } else if (recipe == 1) {
     using S = Strided<RR, NN, +1>;
     hipLaunchKernelGGL((k_ypass_packed<RR, NN, 1>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
-                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+                       static_cast<VV*>(out), static_cast<const VV*>(tw), static_cast<VV*>(nullptr));
   } else if (recipe == 3) {
     using S = Strided<RR, NN, +1>;
     hipLaunchKernelGGL((k_ypass_packed<RR, NN, 3>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
-                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+                       static_cast<VV*>(out), static_cast<const VV*>(tw), static_cast<VV*>(nullptr));
   } else if (recipe == 4) {
     using S = Strided<RR, NN, +1>;
     hipLaunchKernelGGL((k_ypass_packed<RR, NN, 4>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
-                       static_cast<VV*>(out), static_cast<const VV*>(tw));
+                       static_cast<VV*>(out), static_cast<const VV*>(tw), static_cast<VV*>(nullptr));
   } else {
     using S = Strided<RR, NN, -1>;
     hipLaunchKernelGGL((k_ypass_fwd<RR, NN>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
                        static_cast<VV*>(out), static_cast<const VV*>(tw));
   }
+}
+
+// Hessian (3 packed slots to out) and v_max gradient (2 packed slots to gout) in one y pass.
+void ypass_hess_grad(const void* in, void* out, void* gout, const void* tw, hipStream_t s) {
+  using S = Strided<RR, NN, +1>;
+  hipLaunchKernelGGL((k_ypass_packed<RR, NN, 5>), dim3(S::GRID), dim3(S::T), 0, s, static_cast<const VV*>(in),
+                     static_cast<VV*>(out), static_cast<const VV*>(tw), static_cast<VV*>(gout));
 }
 
 void zpass_collapse(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain, hipStream_t s) {
@@ -186,7 +193,7 @@ void collapse_points(const void* t6, size_t count, void* F, double sphere_gain, 
 
 const SizeOps* PIN_CAT(ops_, PIN_INST_FP64, PIN_INST_N)() {
   static const SizeOps ops = {
-      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, xpass_lpt3, ypass, zpass_collapse, zpass_collapse_v,
+      NN, PIN_INST_FP64 != 0, prep, xpass, xpass_fwdinv, xpass_lpt3, ypass, ypass_hess_grad, zpass_collapse, zpass_collapse_v,
       zpass_store, zpass_mu2, zpass_lpt3, grf, reset, redshift, zero, collapse_points,
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},
       LaunchShape{Strided<RR, NN, +1>::GRID, Strided<RR, NN, +1>::T},

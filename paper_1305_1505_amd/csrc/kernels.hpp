@@ -429,32 +429,53 @@ k_xpass_lpt3(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::ty
 //       which the gradient x pass applies itself but the Hessian x pass does not (TI)
 //   three finished components (RECIPE 4, the third-order displacement), packed order x y | z:
 //       (0,0,0) (1,0,0) | (2,0,0)
+//   Hessian and v_max gradient in one pass (RECIPE 5): RECIPE 0's pairs, then RECIPE 3's into a
+//       second output (pairs from SPLIT on), so the Hessian x-pass outputs are read once
 // The z pass maps the packed order back to (xx, xy, xz, yy, yz, zz) and (x, y, z).
+// STREAM: the last transform that reads an input tile streams it (its lines need not stay in L2).
 template <int RECIPE> struct YRecipe;
 template <> struct YRecipe<0> {
-  static constexpr bool TI = false;
-  static constexpr int NIN = 3, NC = 6, Q = 3;
+  static constexpr bool STREAM = true;
+  static constexpr int NIN = 3, NC = 6, Q = 3, SPLIT = 0;
   static constexpr int A[6] = {1, 1, 0, 0, 2, 0}, B[6] = {1, 0, 2, 1, 0, 0}, C[6] = {0, 1, 0, 1, 0, 2};
+  static constexpr bool ti(int) { return false; }
 };
 template <> struct YRecipe<1> {
-  static constexpr bool TI = false;
-  static constexpr int NIN = 2, NC = 3, Q = 2;
+  static constexpr bool STREAM = false;
+  static constexpr int NIN = 2, NC = 3, Q = 2, SPLIT = 0;
   static constexpr int A[3] = {1, 0, 0}, B[3] = {0, 1, 0}, C[3] = {0, 0, 1};
+  static constexpr bool ti(int) { return false; }
 };
 template <> struct YRecipe<3> : YRecipe<1> {
-  static constexpr bool TI = true;
+  static constexpr bool ti(int) { return true; }
 };
 template <> struct YRecipe<4> {
-  static constexpr bool TI = false;
-  static constexpr int NIN = 3, NC = 3, Q = 2;
+  static constexpr bool STREAM = true;
+  static constexpr int NIN = 3, NC = 3, Q = 2, SPLIT = 0;
   static constexpr int A[3] = {0, 1, 2}, B[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+  static constexpr bool ti(int) { return false; }
 };
+template <> struct YRecipe<5> {
+  static constexpr bool STREAM = true;
+  static constexpr int NIN = 3, NC = 9, Q = 5, SPLIT = 3;
+  static constexpr int A[9] = {1, 1, 0, 0, 2, 0, 1, 0, 0}, B[9] = {1, 0, 2, 1, 0, 0, 0, 1, 0},
+                       C[9] = {0, 1, 0, 1, 0, 2, 0, 0, 1};
+  static constexpr bool ti(int c) { return c >= 6; }
+};
+
+// Pair of the last transform that reads input slot `a` under recipe RC.
+template <class RC> constexpr int last_pair(int a) {
+  int q = -1;
+  for (int c = 0; c < RC::NC; ++c)
+    if (RC::A[c] == a) q = c / 2;
+  return q;
+}
 
 template <typename R, int N, int RECIPE>
 __global__ void __launch_bounds__((Strided<R, N, +1>::T))
 __attribute__((amdgpu_waves_per_eu(Strided<R, N, +1>::WPE, Strided<R, N, +1>::WPE)))
 k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* __restrict__ out,
-               const typename Cplx<R>::type* __restrict__ tw) {
+               const typename Cplx<R>::type* __restrict__ tw, typename Cplx<R>::type* __restrict__ out2) {
   using S = Strided<R, N, +1>;
   using RC = YRecipe<RECIPE>;
   using V = typename S::V;
@@ -489,7 +510,7 @@ k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
     const bool has_b = cb < RC::NC;
     const int aa = RC::A[ca];
     const int ab = RC::A[has_b ? cb : ca];
-    V* dst = out + (size_t)q * PSLOT;
+    V* dst = (RC::SPLIT > 0 && q >= RC::SPLIT) ? out2 + (size_t)(q - RC::SPLIT) * PSLOT : out + (size_t)q * PSLOT;
 #pragma unroll
     for (int sgn = 1; sgn >= -1; sgn -= 2) {
       if (!has_b && sgn < 0) break;   // B = 0: C[N - kz] = conj(C[kz]), written below
@@ -513,16 +534,18 @@ k_ypass_packed(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::
           const unsigned off = (unsigned)(jv[k] * HZ + zv[k]);
           // the last transform that reads a tile streams it (Hessian: X_1 after pair 0, X_0 and
           // X_2 after pair 2)
-          const bool last = RC::NIN == 3 && sgn < 0 && (q == 0 || q == RC::Q - 1);
+          const bool final_sgn = sgn < 0 || !has_b;
+          const bool last_a = RC::STREAM && final_sgn && q == last_pair<RC>(aa);
+          const bool last_b = RC::STREAM && final_sgn && q == last_pair<RC>(ab);
           const V* pa = in + aa * S::HSLOT + ubase + off;
-          const V xa = ok[k] ? (last ? ld_stream(pa) : *pa) : V{R(0), R(0)};
+          const V xa = ok[k] ? (last_a ? ld_stream(pa) : *pa) : V{R(0), R(0)};
           V ta = cscale(xa, powf_int(fy, RC::B[ca]) * powf_int(fz, RC::C[ca]));
-          if constexpr (RC::TI) ta = V{-ta.y, ta.x};
+          if (RC::ti(ca)) ta = V{-ta.y, ta.x};
           if (has_b) {
             const V* pb = in + ab * S::HSLOT + ubase + off;
-            const V xb = ab == aa ? xa : (ok[k] ? (last ? ld_stream(pb) : *pb) : V{R(0), R(0)});
+            const V xb = ab == aa ? xa : (ok[k] ? (last_b ? ld_stream(pb) : *pb) : V{R(0), R(0)});
             V tb = cscale(xb, powf_int(fy, RC::B[has_b ? cb : ca]) * powf_int(fz, RC::C[has_b ? cb : ca]));
-            if constexpr (RC::TI) tb = V{-tb.y, tb.x};
+            if (RC::ti(cb)) tb = V{-tb.y, tb.x};
             u[k][s] = sgn > 0 ? V{ta.x - tb.y, ta.y + tb.x} : V{ta.x + tb.y, ta.y - tb.x};
           } else {
             u[k][s] = ta;

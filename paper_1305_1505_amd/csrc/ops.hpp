@@ -31,6 +31,8 @@ struct SizeOps {
   // 2 forward (1 half -> 1 half), 3 gradient times i from the Hessian x pass (2 half -> 2 packed),
   // 4 three finished components (3 half -> 2 packed)
   void (*ypass)(int recipe, const void* in, void* out, const void* tw, hipStream_t s);
+  // Hessian y pass that also writes the v_max gradient (y recipe 3's slots) to gout
+  void (*ypass_hess_grad)(const void* in, void* out, void* gout, const void* tw, hipStream_t s);
   // z pass (packed slots in) with the collapse epilogue at radius index r
   void (*zpass_collapse)(const void* in, const void* tw, void* F, uint8_t* ridx, int r, double sphere_gain,
                          hipStream_t s);

@@ -205,8 +205,7 @@ void plan_run_radii_v(pin_plan p, const void* dk, void* F, uint8_t* ridx, void* 
   for (int r = r0; r < r1; ++r) {
     const void* w = p->window_row(r);
     p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
-    p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
-    p->launch(KC_YPASS_VEL, s, [&] { p->ops->ypass(3, p->X, p->V, p->tw, s); });
+    p->launch(KC_YPASS_VEL, s, [&] { p->ops->ypass_hess_grad(p->X, p->Y, p->V, p->tw, s); });
     p->launch(KC_ZPASS_COLLAPSE_V, s, [&] {
       p->ops->zpass_collapse_v(p->Y, p->V, p->tw, F, ridx, vmax, r, p->sphere_gain, vscale, s);
     });
