@@ -149,7 +149,8 @@ pin_status pin_collapse_times_v(pin_plan plan, const void* dk, void* F, uint8_t*
  * plan (stream-ordered upload; returns when done).  pin_collapse_redshift writes, for each of
  * count values F (device, plan precision), the redshift z_c with D(z_c) = 1/F to zc (device, plan
  * precision); z_c = -1 where F <= 0 or where 1/F is beyond D(a = 1e6) (no collapse).  Computed
- * in float64 (relative error of 1 + z_c below 1e-12).  PIN_ERR_INVALID_ARG without a table. */
+ * in float64 (relative error of 1 + z_c below 1e-12, besides the rounding of z_c itself).
+ * PIN_ERR_INVALID_ARG without a table. */
 pin_status pin_plan_set_growth(pin_plan plan, double omega_m, hipStream_t stream);
 pin_status pin_collapse_redshift(pin_plan plan, const void* F, size_t count, void* zc, hipStream_t stream);
 

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 #include <initializer_list>
 #include <vector>
 
@@ -152,14 +153,20 @@ pin_status pin_plan_set_growth(pin_plan plan, double omega_m, hipStream_t stream
     const GrowthTable g = growth_table(omega_m);
     std::vector<double> host(g.d);
     host.insert(host.end(), g.dd.begin(), g.dd.end());
-    if (plan->growth == nullptr) plan->growth = device_alloc(host.size() * sizeof(double), "growth table");
-    hip_check(hipMemcpyAsync(plan->growth, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, stream),
+    const size_t nd = host.size() * sizeof(double), ng = g.guide.size() * sizeof(int32_t);
+    std::vector<unsigned char> bytes(nd + ng);
+    std::memcpy(bytes.data(), host.data(), nd);
+    std::memcpy(bytes.data() + nd, g.guide.data(), ng);
+    if (plan->growth == nullptr) plan->growth = device_alloc(bytes.size(), "growth table");
+    hip_check(hipMemcpyAsync(plan->growth, bytes.data(), bytes.size(), hipMemcpyHostToDevice, stream),
               "hipMemcpyAsync");
     hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
     plan->growth_y0 = g.y0;
     plan->growth_h = g.h;
     plan->growth_a_per_D = g.a_per_D;
     plan->growth_lom = g.lambda_over_m;
+    plan->growth_gl0 = g.guide_l0;
+    plan->growth_ginv = g.guide_inv;
   });
 }
 
@@ -174,7 +181,9 @@ pin_status pin_collapse_redshift(pin_plan plan, const void* F, size_t count, voi
     const double* d = static_cast<const double*>(plan->growth);
     plan->launch(KC_REDSHIFT, stream, [&] {
       plan->ops->redshift(F, count, d, d + kGrowthNodes, kGrowthNodes, plan->growth_y0, plan->growth_h,
-                          plan->growth_a_per_D, plan->growth_lom, zc, stream);
+                          plan->growth_a_per_D, plan->growth_lom,
+                          reinterpret_cast<const int32_t*>(d + 2 * kGrowthNodes), kGrowthGuide, plan->growth_gl0,
+                          plan->growth_ginv, zc, stream);
     });
   });
 }

@@ -230,6 +230,16 @@ GrowthTable growth_table(double om) {
     g.d[i] = d_unnorm(a, Iy[i]) / norm;
     g.dd[i] = dd_unnorm(a, Iy[i]) / norm;
   }
+  g.guide_l0 = std::log2(g.d[0]);
+  const double hl = (std::log2(g.d[kGrowthNodes - 1]) - g.guide_l0) / (kGrowthGuide - 1);
+  g.guide_inv = 1.0 / hl;
+  g.guide.resize(kGrowthGuide);
+  int node = 0;
+  for (int b = 0; b < kGrowthGuide; ++b) {
+    const double tb = std::exp2(g.guide_l0 + b * hl);
+    while (node + 1 < kGrowthNodes && g.d[node + 1] <= tb) ++node;
+    g.guide[b] = node;
+  }
   return g;
 }
 

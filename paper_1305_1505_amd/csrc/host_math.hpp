@@ -1,6 +1,8 @@
 // Host-side float64 tables and constants of a plan.
 #pragma once
 
+#include <stdint.h>
+
 #include <vector>
 
 namespace pin {
@@ -24,11 +26,16 @@ std::vector<double> radius_ladder(int n, double box, double r_max, double r_min,
                                   double ns);
 // Growing mode of flat LambdaCDM (no radiation), normalised to D(a = 1) = 1, tabulated on
 // y = ln a at kGrowthNodes nodes from ln 1e-3 to ln 1e6: D and dD/dy at each node, and
-// a_per_D = lim_{a->0} a / D (= the unnormalised D at a = 1).
+// a_per_D = lim_{a->0} a / D (= the unnormalised D at a = 1).  guide[b] is the last node with
+// D <= 2^(guide_l0 + b / guide_inv), kGrowthGuide buckets uniform in log2 D over the table: a
+// value's bucket brackets its node interval, so the search for it takes a few steps.
 constexpr int kGrowthNodes = 8192;
+constexpr int kGrowthGuide = 4096;
 struct GrowthTable {
   double y0 = 0, h = 0, a_per_D = 0, lambda_over_m = 0;
   std::vector<double> d, dd;
+  std::vector<int32_t> guide;
+  double guide_l0 = 0, guide_inv = 0;
 };
 GrowthTable growth_table(double omega_m);
 // Amplitude A with sigma^2(8 Mpc/h) = sigma8^2.

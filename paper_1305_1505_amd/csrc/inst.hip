@@ -161,9 +161,10 @@ void reset(void* F, uint8_t* ridx, hipStream_t s) {
 }
 
 void redshift(const void* F, size_t count, const double* d, const double* dd, int m, double y0, double h,
-              double a_per_D, double lambda_over_m, void* z, hipStream_t s) {
+              double a_per_D, double lambda_over_m, const int32_t* guide, int guide_count, double guide_l0,
+              double guide_inv, void* z, hipStream_t s) {
   if (count == 0) return;
-  GrowthArgs g{d, dd, m, y0, h, a_per_D, lambda_over_m};
+  GrowthArgs g{d, dd, m, y0, h, a_per_D, lambda_over_m, guide, guide_count, (float)guide_l0, (float)guide_inv};
   const int block = 256;
   const int grid = (int)((count + block - 1) / block);
   hipLaunchKernelGGL((k_redshift<RR>), dim3(grid), dim3(block), 0, s, static_cast<const RR*>(F), count, g,

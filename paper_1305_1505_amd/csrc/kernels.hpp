@@ -920,6 +920,9 @@ struct GrowthArgs {
   const double* dd;
   int m;
   double y0, h, a_per_D, lambda_over_m;
+  const int32_t* guide;   // last node with d <= 2^(l0 + b / inv), per bucket b < k
+  int k;
+  float l0, inv;
 };
 
 template <typename R>
@@ -935,15 +938,23 @@ __global__ void k_redshift(const R* __restrict__ F, size_t count, GrowthArgs g, 
       const double a = a0 * (1.0 + (2.0 / 11.0) * g.lambda_over_m * a0 * a0 * a0);
       out = 1.0 / a - 1.0;
     } else if (t < g.d[g.m - 1]) {
-      int lo = 0, hi = g.m - 1;   // d[lo] <= t < d[hi]
+      // the bucket of t in log2 narrows the node search to a few steps; the bounds are checked
+      // against t so that a bucket taken one off by rounding only widens the search
+      int b = (int)((__log2f((float)t) - g.l0) * g.inv);
+      b = min(max(b, 0), g.k - 2);
+      int lo = g.guide[b], hi = min(g.guide[b + 1] + 1, g.m - 1);   // d[lo] <= t < d[hi]
+      if (!(g.d[lo] <= t)) lo = 0;
+      if (!(t < g.d[hi])) hi = g.m - 1;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (g.d[mid] <= t) lo = mid; else hi = mid;
       }
       const double d0 = g.d[lo], d1 = g.d[hi], m0 = g.dd[lo] * g.h, m1 = g.dd[hi] * g.h;
+      // Newton on the cubic Hermite segment from the chord: the chord is within h/4 of the root
+      // in s, and each step squares the error times about h, so three steps reach rounding
       double s = (t - d0) / (d1 - d0);
 #pragma unroll
-      for (int it = 0; it < 4; ++it) {
+      for (int it = 0; it < 3; ++it) {
         const double s2 = s * s, s3 = s2 * s;
         const double hv = (2 * s3 - 3 * s2 + 1) * d0 + (s3 - 2 * s2 + s) * m0 + (-2 * s3 + 3 * s2) * d1 + (s3 - s2) * m1;
         const double hp = (6 * s2 - 6 * s) * d0 + (3 * s2 - 4 * s + 1) * m0 + (-6 * s2 + 6 * s) * d1 + (3 * s2 - 2 * s) * m1;

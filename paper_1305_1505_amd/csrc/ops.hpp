@@ -52,7 +52,8 @@ struct SizeOps {
   void (*reset)(void* F, uint8_t* ridx, hipStream_t s);
   // collapse redshift of count F values (growth table on the device, see k_redshift)
   void (*redshift)(const void* F, size_t count, const double* d, const double* dd, int m, double y0, double h,
-                   double a_per_D, double lambda_over_m, void* z, hipStream_t s);
+                   double a_per_D, double lambda_over_m, const int32_t* guide, int guide_count, double guide_l0,
+                   double guide_inv, void* z, hipStream_t s);
   // count reals of the plan's precision set to zero
   void (*zero)(void* p, size_t count, hipStream_t s);
   // per-point collapse model on [6][count] tensors

@@ -96,8 +96,8 @@ struct pin_plan_s {
   pin::FragWorkspace frag;  // fragmentation workspace, allocated on first use
   void* L = nullptr;      // 10 half slots for the third-order displacement, allocated on first use:
                           // T1 as six real fields, then four source slots
-  void* growth = nullptr; // growth table (D then dD/dy, float64) after pin_plan_set_growth
-  double growth_y0 = 0, growth_h = 0, growth_a_per_D = 0, growth_lom = 0;
+  void* growth = nullptr; // growth table (D, dD/dy: float64; search guide: int32) after pin_plan_set_growth
+  double growth_y0 = 0, growth_h = 0, growth_a_per_D = 0, growth_lom = 0, growth_gl0 = 0, growth_ginv = 0;
   size_t slot_bytes = 0;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events[pin::KC_COUNT];

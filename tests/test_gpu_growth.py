@@ -67,3 +67,31 @@ def test_redshift_needs_table(lib):
     with pytest.raises(lib.PinError):
         plan.set_growth(0.0)
     plan.close()
+
+
+@pytest.mark.parametrize("om", [1.0, 0.25])
+def test_redshift_dense_sweep(lib, om):
+    """2^20 values of F log-uniform over the whole table (and beyond its first node), float64.
+    Einstein-de Sitter has the closed form D = a, so z_c = F - 1 for every value; for LambdaCDM
+    z_c must rise strictly with F (a value searched in the wrong node interval would sit on
+    a clamped segment end) and a spread sample solves D(z_c) F = 1 with the oracle's D."""
+    import torch
+
+    plan = lib.Plan(16, 10.0, [1.0], prec=lib.PIN_FP64)
+    plan.set_growth(om)
+    lo = 1e-6 if om == 1.0 else 1.0 / growth.growth_limit(om) * (1.0 + 1e-9)
+    F = np.geomspace(lo, 5e3, 1 << 20)
+    z = plan.collapse_redshift(torch.tensor(F, dtype=torch.float64, device="cuda")).cpu().numpy()
+    plan.close()
+    if om == 1.0:
+        ok = z != -1.0                       # a = 1e6 ends the table: F < 1e-6 reads as never
+        assert np.all(F[~ok] <= 1e-6 * (1.0 + 1e-6)) and ok.sum() > (1 << 20) - 4
+        # 1 + z_c to 1e-12 relative, besides the float64 rounding of z_c itself (as z_c -> -1 that
+        # rounding and that of F - 1 are each 1e-16 / (1 + z_c) relative to 1 + z_c)
+        assert np.all(np.abs(z[ok] - (F[ok] - 1.0)) <= 1e-12 * F[ok] + 2.0 ** -52 * np.abs(z[ok]))
+        return
+    ok = z != -1.0
+    assert np.all(np.diff(z[ok]) > 0.0)
+    idx = np.flatnonzero(ok)[np.linspace(0, ok.sum() - 1, 40).astype(int)]
+    resid = np.array([growth.growth(1.0 / (1.0 + z[i]), om) * F[i] - 1.0 for i in idx])
+    assert np.max(np.abs(resid)) <= 1e-12
