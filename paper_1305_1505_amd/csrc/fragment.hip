@@ -28,6 +28,7 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -40,7 +41,8 @@ namespace {
 constexpr int kNotCollapsed = -2;
 constexpr int kFilament = -1;
 // Order positions considered per round: at 512^3 (z = 0) 2^16, 2^17, 2^18, 2^19 and 2^20 took
-// 191, 150, 134, 137 and 148 ms, with identical labels for every size.
+// 191, 150, 134, 137 and 148 ms, with identical labels for every size (each figure then included
+// ~37 ms of host quadrature for the sigma nodes, now computed once per plan).
 constexpr int kWindow = 1 << 18;
 constexpr int kRoundsPerCheck = 32;    // rounds queued between host checks of progress
 constexpr int kRadiusTable = 1 << 20;  // halo radii tabulated for N_h up to this
@@ -543,7 +545,10 @@ void fragment_prepare(FragWorkspace& w, int n, double box, double amplitude, dou
     hip_check(hipMemcpyAsync(w.rtab, rt.data(), rt.size() * 8, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
-  // sigma nodes: R_k = R(1) 2^(k/64) cells up to the radius of the whole grid
+  // sigma nodes: R_k = R(1) 2^(k/64) cells up to the radius of the whole grid (a host quadrature
+  // per node, tens of milliseconds at 512^3: kept while the box and the spectrum stay the same)
+  const double key[4] = {box, amplitude, gamma, ns};
+  if (w.stab_n > 0 && std::equal(key, key + 4, w.s_for)) return;
   w.s_r0 = std::pow(3.0 * 1 / (4.0 * kPi), 1.0 / 3.0);
   w.s_step = std::log(2.0) / kNodesPerOctave;
   const double rmax = std::pow(3.0 * (double)vol / (4.0 * kPi), 1.0 / 3.0);
@@ -552,6 +557,7 @@ void fragment_prepare(FragWorkspace& w, int n, double box, double amplitude, dou
   const std::vector<double> st = tophat_sigma_nodes(w.s_r0 * box / n, w.s_step, w.stab_n, amplitude, gamma, ns);
   hip_check(hipMemcpyAsync(w.stab, st.data(), st.size() * 8, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+  std::copy(key, key + 4, w.s_for);
 }
 
 int fragment_run(FragWorkspace& w, bool fp64, int n, const void* F, const void* v, double uscale, double f_min,

@@ -38,6 +38,7 @@ struct FragWorkspace {
   double* stab = nullptr;         // sigma(R) nodes
   int stab_n = 0;
   double s_r0 = 0, s_step = 0;
+  double s_for[4] = {0, 0, 0, 0};   // box, amplitude, gamma, ns the nodes were computed for
   int32_t* host_ctl = nullptr;    // pinned mirror of ctl
   int n_halos = -1;               // halos of the last fragment_run (-1: none yet)
   int n_mergers = 0;              // its merger events
@@ -48,7 +49,8 @@ struct FragWorkspace {
 size_t fragment_workspace_bytes(int n);
 
 // Allocate (first call) and fill the radius table and the sigma nodes (top-hat rms of the linear
-// field at z = 0, 64 nodes per octave in R from the radius of one particle); returns on completion.
+// field at z = 0, 64 nodes per octave in R from the radius of one particle; recomputed only when
+// the box or the spectrum changes); returns on completion.
 void fragment_prepare(FragWorkspace& w, int n, double box, double amplitude, double gamma, double ns,
                       hipStream_t s);
 void fragment_free(FragWorkspace& w);
