@@ -30,7 +30,7 @@ def oracle_inputs(n, box, seed, n_radii):
     return F.ravel(), v.reshape(3, -1), radii
 
 
-def _run_both(lib, n, box, seed, prec, f_min, n_radii=12):
+def _run_both(lib, n, box, seed, prec, f_min, n_radii=12, params=None):
     import torch
 
     F, v, radii = oracle_inputs(n, box, seed, n_radii)
@@ -39,7 +39,12 @@ def _run_both(lib, n, box, seed, prec, f_min, n_radii=12):
     plan = lib.Plan(n, box, radii, sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=prec)
     tF = torch.from_numpy(Fq.reshape(n, n, n)).cuda()
     tv = torch.from_numpy(vq.reshape(3, n, n, n)).cuda()
-    label, sizes, count = plan.fragment(tF, tv, f_min)
+    cparams = None
+    if params is not None:
+        cparams = lib.pin_fragment_default_params()
+        for k, val in params.items():
+            setattr(cparams, k, val)
+    label, sizes, count = plan.fragment(tF, tv, f_min, params=cparams)
     cat = [t.cpu().numpy() for t in plan.fragment_catalog(count)]
     mer = [t.cpu().numpy() for t in plan.fragment_mergers()]
     torch.cuda.synchronize()
@@ -49,7 +54,8 @@ def _run_both(lib, n, box, seed, prec, f_min, n_radii=12):
           f"{int(np.sum(label >= 0))} in halos", flush=True)
     sigma = FR.SigmaTable(n, box, W.SIGMA8, W.GAMMA, W.NS, nh_max=n ** 3)
     ref, ref_sizes, ref_cat, ref_mer = FR.fragment(Fq.astype(np.float64), vq.astype(np.float64) * (n / box), f_min, n,
-                                                   sigma, catalog_cell=box / n, want_mergers=True)
+                                                   sigma, params=params or FR.TABLE1, catalog_cell=box / n,
+                                                   want_mergers=True)
     # merger history: the same events in the same order
     print(f"[fragment] {len(ref_mer)} mergers", flush=True)
     assert len(mer[0]) == len(ref_mer)
@@ -86,6 +92,23 @@ def test_fragment_fp32_matches_oracle_128(lib):
     n = 128
     label, sizes, count, ref, ref_sizes = _run_both(lib, n, 200.0, 14, lib.PIN_FP32, 1.0, n_radii=8)
     assert count == len(ref_sizes)
+    assert np.array_equal(label, ref)
+    expect = np.zeros(n ** 3, dtype=np.int64)
+    for h, sz in ref_sizes.items():
+        expect[h] = sz
+    assert np.array_equal(sizes, expect)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("params,f_min", [
+    ({"f_a": 0.40, "f_ra": 0.10, "f_s": 0.10, "f_m": 0.60, "f_rm": 1.00}, 1.0),    # merges more readily
+    ({"f_a": 0.20, "f_ra": 0.25, "f_s": 0.02, "f_m": 0.25, "f_rm": 0.40}, 1.3),    # fewer mergers, z > 0
+])
+def test_fragment_custom_params_match_oracle(lib, params, f_min):
+    """Other accretion and merging constants than Table 1's, and an output time before z = 0."""
+    n = 48
+    label, sizes, count, ref, ref_sizes = _run_both(lib, n, 75.0, 12, lib.PIN_FP32, f_min, params=params)
+    assert count == len(ref_sizes) and count > 1
     assert np.array_equal(label, ref)
     expect = np.zeros(n ** 3, dtype=np.int64)
     for h, sz in ref_sizes.items():
