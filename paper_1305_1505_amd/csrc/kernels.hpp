@@ -101,13 +101,30 @@ template <typename R, int N, int Q> struct ZTile {
   static constexpr int T = P * M0;
 };
 
+// The prepared half slot g0 (k_prep's output, read only by the Hessian x pass): tiled where W
+// divides N/2, so that an x-pass workgroup (one y, W consecutive z, all x) reads one contiguous
+// block of N W elements instead of W elements every 1 MB at 512^3 (x pass 0.494 -> 0.463 ms);
+// rows (x, y, z) otherwise.
+template <typename R, int N> struct PrepLayout {
+  static constexpr int W = Tile<R>::PS;
+  static constexpr int HZ = N / 2;
+  static constexpr bool TILED = HZ % W == 0;
+  __device__ static __forceinline__ size_t index(int x, int y, int z) {
+    if constexpr (TILED) {
+      return (((size_t)y * (HZ / W) + z / W) * N + x) * W + z % W;
+    } else {
+      return ((size_t)x * N + y) * HZ + z;
+    }
+  }
+};
+
 // Packed z lines, the y pass's output and the z pass's input: N lines of N complex per x-plane,
 // element n of line (x, y) at `index(x, y, n)`.  Tiled where the widths allow: positions in
 // groups of W (one y-pass tile row, 128 bytes), and for each x and group the N lines' W elements
 // one after another.  A y-pass workgroup then writes whole contiguous blocks (N W elements per
-// group) instead of W elements every line (y pass 0.97 -> 0.87 ms for the same bytes at 512^3),
-// and a z-pass wave still reads W consecutive elements per group.  The z pass steps through its
-// elements M0 = N/R0 positions apart, which must stay in the same column of a group.
+// group) instead of W elements every line (y pass 1.02 -> 0.96 ms at 512^3), and a z-pass wave
+// still reads W consecutive elements per group.  The z pass steps through its elements
+// M0 = N/R0 positions apart, which must stay in the same column of a group.
 template <typename R, int N> struct PackedLayout {
   static constexpr int W = Tile<R>::PS;
   static constexpr int M0 = N / factorize(N).r[0];
@@ -158,8 +175,8 @@ __device__ __forceinline__ void load_twiddles(V* __restrict__ s_tw, const V* __r
 
 // ---------------------------------------------------------------------------------------------
 // Radius-independent part of the Hessian multiplier, once per call: g0 = M dk scale / f^2 into
-// a half slot whose rows are 128-byte aligned (the user spectrum's rows of N/2+1 complex are
-// not), so the per-radius x pass reads whole cache lines.
+// a half slot in the x pass's tile order (PrepLayout; the user spectrum's rows of N/2+1 complex
+// are neither aligned nor in that order), so the per-radius x pass reads contiguous blocks.
 template <typename R, int N>
 __global__ void k_prep(const typename Cplx<R>::type* __restrict__ dk, typename Cplx<R>::type* __restrict__ g0,
                        R scale) {
@@ -180,11 +197,11 @@ __global__ void k_prep(const typename Cplx<R>::type* __restrict__ dk, typename C
       out = V{d.x * m, d.y * m};
     }
   }
-  st_stream(&g0[i], out);
+  st_stream(&g0[PrepLayout<R, N>::index(x, y, z)], out);
 }
 
 // ---------------------------------------------------------------------------------------------
-// x pass.  MODE 0 (Hessian): input g0 (aligned half slot from k_prep), 3 outputs, multiplier
+// x pass.  MODE 0 (Hessian): input g0 (k_prep's tiled half slot), 3 outputs, multiplier
 // W(x)W(y)W(z) from the window row wtab (never null; a row of ones for no smoothing).  MODE 1
 // (gradient): input the user half spectrum, 2 outputs, multiplier i * scale / f^2 (wtab
 // unused).  Outputs: half slots.  Loads are unconditional (lanes without an element read an
@@ -225,7 +242,7 @@ k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
         const int n = j + s * M;
         V val = V{R(0), R(0)};
         if (ok) {
-          val = in[((size_t)n * N + y) * HZ + z];
+          val = in[PrepLayout<R, N>::index(n, y, z)];
           if (wtab != nullptr) val = cscale(val, wtab[n] * wyz);
         }
         u[0][s] = cscale(val, powf_int(R(ifreq(n, N)), a));
@@ -270,7 +287,7 @@ k_xpass(const typename Cplx<R>::type* __restrict__ in, typename Cplx<R>::type* _
         V val;
         if constexpr (MODE == 0) {
           // no mask: a lane without an element never writes its values (to LDS or out)
-          val = cscale(in[((size_t)n * N + y) * HZ + z], wtab[n] * wyz[k] * fa);
+          val = cscale(in[PrepLayout<R, N>::index(n, y, z)], wtab[n] * wyz[k] * fa);
         } else {
           const V d = in[((size_t)n * N + y) * NH + z];
           const int fx = ifreq(n, N);
