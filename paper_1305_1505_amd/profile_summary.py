@@ -3,13 +3,18 @@
     python -m paper_1305_1505_amd.profile_summary trace  <kernel_stats.csv> [out.md]
     python -m paper_1305_1505_amd.profile_summary traffic <fetch counter_collection.csv>
                                                          <write counter_collection.csv> <out.json> [out.md]
+    python -m paper_1305_1505_amd.profile_summary issue <SQ counter_collection.csv> [out.md]
 
 `trace` turns a `rocprofv3 --kernel-trace --stats --output-format csv` kernel-stats file into a
 markdown table.  `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
 `bench.py --copy-probe` into HBM bytes per dispatch for each kernel, each counter scaled by what
 it reads for the plain device copies of the probe (three 1 GiB copies,
 `__amd_rocclr_copyBuffer`, all dispatches together), and records the hash of the kernel sources the counters belong to:
-`bench.py` reports the traffic only while the sources still hash to that value.
+`bench.py` reports the traffic only while the sources still hash to that value.  `issue` turns
+one `rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD
+SQ_INSTS_VMEM_WR ...` run into instructions per wave for the three per-radius passes, and the
+time their VALU instructions alone take to issue: one wave64 instruction per 4 cycles on each
+of the 1024 SIMDs (256 CUs x 4, 16 lanes each), at 2.4 GHz.
 """
 
 import csv
@@ -94,6 +99,36 @@ def traffic_table(t):
     return "\n".join(lines)
 
 
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+
+
+def issue_table(sq_csv):
+    counters = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")
+    per = {c: per_kernel_counter(sq_csv, c) for c in counters}
+    dur = {}
+    for r in _rows(sq_csv):
+        dur.setdefault(r["Kernel_Name"], {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    lines = ["| kernel | dispatches | waves | VALU / wave | SALU / wave | LDS / wave | VMEM rd / wave | "
+             "VMEM wr / wave | VALU issue time | dispatch time (counter run) |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for cls, key in KERNEL_KEYS.items():
+        avg = {}
+        for c in counters:
+            vals = [v for k, gvs in per[c].items() if key in k for _, v in gvs]
+            avg[c] = sum(vals) / len(vals) if vals else float("nan")
+        ds = [d for k, dd in dur.items() if key in k for d in dd.values()]
+        if not ds:
+            continue
+        waves = avg["SQ_WAVES"]
+        valu_ms = avg["SQ_INSTS_VALU"] * 4 / SIMDS / CLOCK_HZ * 1e3
+        lines.append(f"| {cls} | {len(ds)} | {waves:.0f} | {avg['SQ_INSTS_VALU'] / waves:.0f} | "
+                     f"{avg['SQ_INSTS_SALU'] / waves:.0f} | {avg['SQ_INSTS_LDS'] / waves:.0f} | "
+                     f"{avg['SQ_INSTS_VMEM_RD'] / waves:.1f} | {avg['SQ_INSTS_VMEM_WR'] / waves:.1f} | "
+                     f"{valu_ms:.3f} ms | {sum(ds) / len(ds) / 1e6:.3f} ms |")
+    return "\n".join(lines)
+
+
 def trace_table(stats_csv):
     rows = _rows(stats_csv)
     lines = ["| kernel | calls | total ns | average ns | % |", "|---|---:|---:|---:|---:|"]
@@ -108,6 +143,12 @@ def trace_table(stats_csv):
 def main(argv):
     if len(argv) >= 2 and argv[0] == "trace":
         table = trace_table(argv[1])
+        if len(argv) > 2:
+            with open(argv[2], "a") as fh:
+                fh.write(table + "\n")
+        print(table)
+    elif len(argv) >= 2 and argv[0] == "issue":
+        table = issue_table(argv[1])
         if len(argv) > 2:
             with open(argv[2], "a") as fh:
                 fh.write(table + "\n")
