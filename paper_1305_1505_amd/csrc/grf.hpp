@@ -7,7 +7,8 @@
 // Uniforms u = (2*(w >> 12) + 1) * 2^-53 from w = c1:c0 and c3:c2; Box-Muller in float64.
 // Spectrum: P(k) = A k^ns T(k/Gamma)^2 with the BBKS transfer function
 //   T(q) = ln(1 + 2.34 q)/(2.34 q) [1 + 3.89 q + (16.1 q)^2 + (5.46 q)^3 + (6.71 q)^4]^(-1/4),
-// and dk = sqrt(P(k) N^6 / (2 L^3)) (g1 + i g2).  On the l = 0 plane the member of each
+// and dk = sqrt(P(k) N^6 / (2 L^3)) (g1 + i g2), the amplitude read from the plan's table by
+// f^2 (computed on the host in float64 from the formula above).  On the l = 0 plane the member of each
 // (f, -f) pair with the larger i*N + j is drawn, its partner is the conjugate; k = 0 and all
 // Nyquist modes are zero.
 #pragma once
@@ -51,21 +52,11 @@ __device__ __forceinline__ double uniform_from_words(uint32_t lo, uint32_t hi) {
 
 struct GrfArgs {
   uint64_t seed;
-  double norm;       // A * N^6 / (2 L^3)
-  double kf;         // 2 pi / L
-  double gamma;
-  double ns;
+  // sqrt(P(k) A N^6 / (2 L^3)) by f^2 = fx^2 + fy^2 + fz^2 (the spectrum depends on |k| only, and
+  // |k|^2 takes the 3 (N/2)^2 + 1 integer values of f^2 times (2 pi / L)^2), computed once per
+  // plan in float64 on the host
+  const double* amp;
 };
-
-__device__ __forceinline__ double bbks_power_unit(double k, double gamma, double ns) {
-  const double q = k / gamma;
-  const double x = 2.34 * q;
-  const double lead = log1p(x) / x;
-  const double a = 16.1 * q, b = 5.46 * q, c = 6.71 * q;
-  const double poly = 1.0 + 3.89 * q + a * a + b * b * b + (c * c) * (c * c);
-  const double tk = lead / sqrt(sqrt(poly));
-  return pow(k, ns) * tk * tk;
-}
 
 template <typename R>
 __global__ void k_grf(typename Cplx<R>::type* __restrict__ dk, int n, GrfArgs g) {
@@ -101,9 +92,8 @@ __global__ void k_grf(typename Cplx<R>::type* __restrict__ dk, int n, GrfArgs g)
   const double rad = sqrt(-2.0 * log(u1));
   const double ang = 2.0 * 3.14159265358979323846 * u2;
   const double g1 = rad * cos(ang), g2 = rad * sin(ang);
-  const double fi = i < h ? i : i - n, fj = j < h ? j : j - n, fl = l;
-  const double kmag = g.kf * sqrt(fi * fi + fj * fj + fl * fl);
-  const double amp = sqrt(bbks_power_unit(kmag, g.gamma, g.ns) * g.norm);
+  const int fi = i < h ? i : i - n, fj = j < h ? j : j - n;
+  const double amp = g.amp[fi * fi + fj * fj + l * l];
   double re = amp * g1, im = amp * g2;
   if (cj_conj) im = -im;
   dk[idx] = V{(R)re, (R)im};

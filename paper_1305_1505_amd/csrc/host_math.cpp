@@ -243,6 +243,19 @@ GrowthTable growth_table(double om) {
   return g;
 }
 
+std::vector<double> mode_amplitudes(int n, double box, double amplitude, double gamma, double ns) {
+  const int h = n / 2;
+  std::vector<double> a((size_t)3 * h * h + 1, 0.0);
+  const double norm = amplitude * std::pow((double)n, 6) / (2.0 * box * box * box);
+  const double kf = 2.0 * 3.14159265358979323846 / box;
+  for (size_t f2 = 1; f2 < a.size(); ++f2) {
+    const double k = kf * std::sqrt((double)f2);
+    const double t = bbks_transfer(k, gamma);
+    a[f2] = std::sqrt(std::pow(k, ns) * t * t * norm);
+  }
+  return a;
+}
+
 double amplitude_for_sigma8(double sigma8, double gamma, double ns) {
   return sigma8 * sigma8 / sigma2_tophat_unit(8.0, gamma, ns);
 }

@@ -40,6 +40,10 @@ struct GrowthTable {
 GrowthTable growth_table(double omega_m);
 // Amplitude A with sigma^2(8 Mpc/h) = sigma8^2.
 double amplitude_for_sigma8(double sigma8, double gamma, double ns);
+// Mode amplitudes of an N^3 field in a box of side L: entry f2 = fx^2 + fy^2 + fz^2 (integer
+// frequencies, 0 <= f2 <= 3 (N/2)^2) holds sqrt(P(k) norm), k = (2 pi / L) sqrt(f2), P the BBKS
+// spectrum of amplitude A, norm = N^6 / (2 L^3); entry 0 is 0.
+std::vector<double> mode_amplitudes(int n, double box, double amplitude, double gamma, double ns);
 // Root of the 3rd-order EdS sphere series 1 - x/3 - x^2/21 - 23 x^3/1701 (bisection), and the
 // EdS linear collapse threshold (3/20)(12 pi)^(2/3).
 double eds_sphere_root();

@@ -145,8 +145,8 @@ void zpass_lpt3(const void* in, const void* t1, const void* tw, void* out_slots,
                      static_cast<const VV*>(in), static_cast<const VV*>(tw), a);
 }
 
-void grf(void* dk, uint64_t seed, double norm, double kf, double gamma, double ns, hipStream_t s) {
-  GrfArgs g{seed, norm, kf, gamma, ns};
+void grf(void* dk, uint64_t seed, const double* amp, hipStream_t s) {
+  GrfArgs g{seed, amp};
   const size_t total = (size_t)NN * NN * (NN / 2 + 1);
   const int block = 256;
   const int grid = (int)((total + block - 1) / block);

@@ -48,7 +48,8 @@ struct SizeOps {
   // z pass of the second-order tensor with the third-order source epilogue: reads T1 [6][N^3],
   // writes the z-forward transforms of (sl, cx, cy, cz) to four half slots
   void (*zpass_lpt3)(const void* in, const void* t1, const void* tw, void* out_slots, hipStream_t s);
-  void (*grf)(void* dk, uint64_t seed, double norm, double kf, double gamma, double ns, hipStream_t s);
+  // the field of `seed`, mode amplitudes from the plan's table (mode_amplitudes)
+  void (*grf)(void* dk, uint64_t seed, const double* amp, hipStream_t s);
   void (*reset)(void* F, uint8_t* ridx, hipStream_t s);
   // collapse redshift of count F values (growth table on the device, see k_redshift)
   void (*redshift)(const void* F, size_t count, const double* d, const double* dd, int m, double y0, double h,

@@ -125,6 +125,11 @@ pin_plan plan_create(const pin_plan_desc* desc, int radii_capacity) {
     p->Y = device_alloc(6 * p->slot_bytes, "workspace Y");
     p->G = device_alloc(p->slot_bytes, "workspace G");
     upload(p->tw, twiddles(p->n), p->fp64, nullptr);
+    {
+      const std::vector<double> a = mode_amplitudes(p->n, p->box, p->amplitude, p->gamma, p->ns);
+      p->amp = device_alloc(a.size() * sizeof(double), "mode amplitudes");
+      hip_check(hipMemcpy(p->amp, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+    }
     upload(p->window_row(p->nr_capacity), std::vector<double>((size_t)p->n, 1.0), p->fp64, nullptr);
     plan_set_radii(p, desc->radii_cells, desc->n_radii, nullptr);
   } catch (...) {
@@ -143,6 +148,7 @@ void plan_free(pin_plan p) {
     }
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   if (p->tw) (void)hipFree(p->tw);
+  if (p->amp) (void)hipFree(p->amp);
   if (p->wtab) (void)hipFree(p->wtab);
   if (p->X) (void)hipFree(p->X);
   if (p->Y) (void)hipFree(p->Y);
@@ -168,10 +174,7 @@ void plan_set_radii(pin_plan p, const double* radii, int n_radii, hipStream_t s)
 }
 
 void plan_generate_field(pin_plan p, uint64_t seed, void* dk, hipStream_t s) {
-  const double n = p->n;
-  const double norm = p->amplitude * std::pow(n, 6) / (2.0 * p->box * p->box * p->box);
-  const double kf = 2.0 * 3.14159265358979323846 / p->box;
-  p->launch(KC_GRF, s, [&] { p->ops->grf(dk, seed, norm, kf, p->gamma, p->ns, s); });
+  p->launch(KC_GRF, s, [&] { p->ops->grf(dk, seed, static_cast<const double*>(p->amp), s); });
 }
 
 void plan_reset(pin_plan p, void* F, uint8_t* ridx, hipStream_t s) {
