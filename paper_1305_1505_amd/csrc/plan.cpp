@@ -100,6 +100,28 @@ void check_device_range(const void* p, size_t bytes, const char* name) {
     fail(PIN_ERR_INVALID_ARG, std::string(name) + " is smaller than required (" + std::to_string(bytes) + " bytes)");
 }
 
+// The mode-amplitude table for the plan's current box: computed on the host (float64) and
+// uploaded on first use of that box, kept for later calls; at most kAmpTables boxes are kept,
+// the oldest freed first (hipFree waits for any kernel still reading it).
+constexpr size_t kAmpTables = 8;
+static const double* amp_table(pin_plan p) {
+  for (auto& t : p->amp_tables)
+    if (t.first == p->box) return static_cast<const double*>(t.second);
+  if (p->amp_tables.size() >= kAmpTables) {
+    (void)hipFree(p->amp_tables.front().second);
+    p->amp_tables.erase(p->amp_tables.begin());
+  }
+  const std::vector<double> a = mode_amplitudes(p->n, p->box, p->amplitude, p->gamma, p->ns);
+  void* d = device_alloc(a.size() * sizeof(double), "mode amplitudes");
+  const hipError_t e = hipMemcpy(d, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    hip_check(e, "hipMemcpy");
+  }
+  p->amp_tables.emplace_back(p->box, d);
+  return static_cast<const double*>(d);
+}
+
 pin_plan plan_create(const pin_plan_desc* desc, int radii_capacity) {
   validate_desc(desc);
   if (radii_capacity < desc->n_radii) radii_capacity = desc->n_radii;
@@ -125,11 +147,7 @@ pin_plan plan_create(const pin_plan_desc* desc, int radii_capacity) {
     p->Y = device_alloc(6 * p->slot_bytes, "workspace Y");
     p->G = device_alloc(p->slot_bytes, "workspace G");
     upload(p->tw, twiddles(p->n), p->fp64, nullptr);
-    {
-      const std::vector<double> a = mode_amplitudes(p->n, p->box, p->amplitude, p->gamma, p->ns);
-      p->amp = device_alloc(a.size() * sizeof(double), "mode amplitudes");
-      hip_check(hipMemcpy(p->amp, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
-    }
+    (void)amp_table(p);
     upload(p->window_row(p->nr_capacity), std::vector<double>((size_t)p->n, 1.0), p->fp64, nullptr);
     plan_set_radii(p, desc->radii_cells, desc->n_radii, nullptr);
   } catch (...) {
@@ -148,7 +166,7 @@ void plan_free(pin_plan p) {
     }
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   if (p->tw) (void)hipFree(p->tw);
-  if (p->amp) (void)hipFree(p->amp);
+  for (auto& t : p->amp_tables) (void)hipFree(t.second);
   if (p->wtab) (void)hipFree(p->wtab);
   if (p->X) (void)hipFree(p->X);
   if (p->Y) (void)hipFree(p->Y);
@@ -174,7 +192,8 @@ void plan_set_radii(pin_plan p, const double* radii, int n_radii, hipStream_t s)
 }
 
 void plan_generate_field(pin_plan p, uint64_t seed, void* dk, hipStream_t s) {
-  p->launch(KC_GRF, s, [&] { p->ops->grf(dk, seed, static_cast<const double*>(p->amp), s); });
+  const double* amp = amp_table(p);
+  p->launch(KC_GRF, s, [&] { p->ops->grf(dk, seed, amp, s); });
 }
 
 void plan_reset(pin_plan p, void* F, uint8_t* ridx, hipStream_t s) {

@@ -88,7 +88,9 @@ struct pin_plan_s {
   const pin::SizeOps* ops = nullptr;
   int device = 0;
   void* tw = nullptr;
-  void* amp = nullptr;    // mode amplitudes by f^2 (float64, mode_amplitudes), for the field
+  // mode amplitudes by f^2 (float64, mode_amplitudes) for the field, one table per box the plan
+  // has generated fields for (a serving slot changes its box per request), oldest first
+  std::vector<std::pair<double, void*>> amp_tables;
   void* wtab = nullptr;   // (nr_capacity + 1) rows of N window values
   void* X = nullptr;      // 4 half slots (= 2 packed slots)
   void* Y = nullptr;      // 6 half slots (= 3 packed slots)
