@@ -9,8 +9,10 @@ Workload (default): 512^3 grid, 1000 Mpc/h box, 40 Gaussian radii log-spaced 60 
 BBKS spectrum (Gamma 0.21, n 1, sigma_8 0.8), complex64 FFTs.  Data are synthetic (seeded).
 
 Prints ONE JSON line.  Extra fields: the dominant kernel's roofline (algorithmic bytes per launch
-over its HIP-event-timed average duration), the collapse-only rate, the float64 rate of the same
-workload, and the FP64 CPU oracle timed on a bounded sample (cpu_baseline).
+over its HIP-event-timed average duration; HBM traffic and VALU issue time per launch from the
+committed rocprofv3 counter summaries while the kernel sources match them), the collapse-only
+rate, the float64 rate of the same workload, and the FP64 CPU oracle timed on a bounded sample
+(cpu_baseline).
 """
 
 import argparse
@@ -54,6 +56,22 @@ def measured_traffic(cls, n, prec):
     k = t["kernels"][cls]
     return {"bytes": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
             "write_bytes": k["write_bytes"], "source": "profiles/traffic_c512_fp32.json"}
+
+
+def measured_issue(cls, n, prec):
+    """Time the VALU instructions of kernel `cls` take to issue (ns per launch), from the committed
+    SQ counter summary, if it was taken on the current kernel sources at this workload; else None."""
+    from paper_1305_1505_amd import binding as B
+    from paper_1305_1505_amd import profile_summary
+
+    path = os.path.join(ROOT, "profiles", "issue_c512_fp32.json")
+    if n != 512 or prec != B.PIN_FP32 or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256") != profile_summary.kernel_source_hash() or cls not in t["kernels"]:
+        return None
+    return t["kernels"][cls]["valu_issue_ns"]
 
 
 def cpu_baseline(sample_n=64, radius_stride=1):
@@ -280,6 +298,10 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(measured["bytes"]) if measured else None,
                 "traffic_detail": measured, "bytes_per_launch": dom_bytes}
+    # the VALU side: the time the kernel's VALU instructions take to issue (committed SQ counters,
+    # one wave64 instruction per 4 cycles per SIMD at 2.4 GHz) over its measured launch time
+    issue_ns = measured_issue(dom, n, prec)
+    roofline["valu_issue_frac"] = round(issue_ns / (kernels[dom]["avg_ms"] * 1e6), 4) if issue_ns else None
     per_kernel = {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"],
                       "GB/s": (round(algorithmic_bytes(k, n, real_bytes) / (v["avg_ms"] * 1e-3) / 1e9, 1)
                                if algorithmic_bytes(k, n, real_bytes) else None)}

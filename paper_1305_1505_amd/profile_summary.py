@@ -3,7 +3,7 @@
     python -m paper_1305_1505_amd.profile_summary trace  <kernel_stats.csv> [out.md]
     python -m paper_1305_1505_amd.profile_summary traffic <fetch counter_collection.csv>
                                                          <write counter_collection.csv> <out.json> [out.md]
-    python -m paper_1305_1505_amd.profile_summary issue <SQ counter_collection.csv> [out.md]
+    python -m paper_1305_1505_amd.profile_summary issue <SQ counter_collection.csv> <out.json> [out.md]
 
 `trace` turns a `rocprofv3 --kernel-trace --stats --output-format csv` kernel-stats file into a
 markdown table.  `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
@@ -103,29 +103,40 @@ SIMDS = 1024
 CLOCK_HZ = 2.4e9
 
 
-def issue_table(sq_csv):
+def issue(sq_csv):
+    """Per-dispatch averages of the SQ instruction counters for the three passes, with the hash of
+    the kernel sources."""
     counters = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")
     per = {c: per_kernel_counter(sq_csv, c) for c in counters}
     dur = {}
     for r in _rows(sq_csv):
         dur.setdefault(r["Kernel_Name"], {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-    lines = ["| kernel | dispatches | waves | VALU / wave | SALU / wave | LDS / wave | VMEM rd / wave | "
-             "VMEM wr / wave | VALU issue time | dispatch time (counter run) |",
-             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    kernels = {}
     for cls, key in KERNEL_KEYS.items():
+        ds = [d for k, dd in dur.items() if key in k for d in dd.values()]
+        if not ds:
+            continue
         avg = {}
         for c in counters:
             vals = [v for k, gvs in per[c].items() if key in k for _, v in gvs]
             avg[c] = sum(vals) / len(vals) if vals else float("nan")
-        ds = [d for k, dd in dur.items() if key in k for d in dd.values()]
-        if not ds:
-            continue
+        kernels[cls] = {"dispatches": len(ds), "counters": avg, "dispatch_ns": sum(ds) / len(ds),
+                        "valu_issue_ns": avg["SQ_INSTS_VALU"] * 4 / SIMDS / CLOCK_HZ * 1e9}
+    return {"kernel_source_sha256": kernel_source_hash(), "simds": SIMDS, "clock_hz": CLOCK_HZ, "kernels": kernels}
+
+
+def issue_table(t):
+    lines = ["| kernel | dispatches | waves | VALU / wave | SALU / wave | LDS / wave | VMEM rd / wave | "
+             "VMEM wr / wave | VALU issue time | dispatch time (counter run) |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for cls, k in t["kernels"].items():
+        avg = k["counters"]
         waves = avg["SQ_WAVES"]
-        valu_ms = avg["SQ_INSTS_VALU"] * 4 / SIMDS / CLOCK_HZ * 1e3
-        lines.append(f"| {cls} | {len(ds)} | {waves:.0f} | {avg['SQ_INSTS_VALU'] / waves:.0f} | "
+        lines.append(f"| {cls} | {k['dispatches']} | {waves:.0f} | {avg['SQ_INSTS_VALU'] / waves:.0f} | "
                      f"{avg['SQ_INSTS_SALU'] / waves:.0f} | {avg['SQ_INSTS_LDS'] / waves:.0f} | "
                      f"{avg['SQ_INSTS_VMEM_RD'] / waves:.1f} | {avg['SQ_INSTS_VMEM_WR'] / waves:.1f} | "
-                     f"{valu_ms:.3f} ms | {sum(ds) / len(ds) / 1e6:.3f} ms |")
+                     f"{k['valu_issue_ns'] / 1e6:.3f} ms | {k['dispatch_ns'] / 1e6:.3f} ms |")
+    lines.append(f"\nkernel sources sha256: `{t['kernel_source_sha256']}`")
     return "\n".join(lines)
 
 
@@ -147,10 +158,14 @@ def main(argv):
             with open(argv[2], "a") as fh:
                 fh.write(table + "\n")
         print(table)
-    elif len(argv) >= 2 and argv[0] == "issue":
-        table = issue_table(argv[1])
-        if len(argv) > 2:
-            with open(argv[2], "a") as fh:
+    elif len(argv) >= 3 and argv[0] == "issue":
+        t = issue(argv[1])
+        with open(argv[2], "w") as fh:
+            json.dump(t, fh, indent=1)
+            fh.write("\n")
+        table = issue_table(t)
+        if len(argv) > 3:
+            with open(argv[3], "a") as fh:
                 fh.write(table + "\n")
         print(table)
     elif len(argv) >= 4 and argv[0] == "traffic":
