@@ -96,6 +96,33 @@ def test_served_results_bitwise_equal_plain_path_in_a_mix(lib):
         assert np.array_equal(a, b)
 
 
+def test_one_slot_many_boxes(lib):
+    """One slot of one size class serves requests of eleven different boxes in turn, the first
+    again at the end: the field's mode amplitudes follow each request's box (the plan keeps a
+    table per box, at most eight, the oldest dropped), so every result equals the plain path's."""
+    import torch
+
+    B = lib
+    boxes = [16.0 + 4.0 * i for i in range(11)] + [16.0]
+    reqs = [dict(seed=40 + i, n=16, box=bx, radii=W.radii_cells(3, 4.0, 0.75), disp=1) for i, bx in enumerate(boxes)]
+    cfg = B.make_serve_config(40e9, max_slots_per_class=1)
+    srv = B.pin_serve_create(cfg)
+    served = []
+    try:
+        for r in reqs:
+            t = B.pin_serve_submit(srv, B.make_request(r["seed"], r["n"], r["box"], r["radii"], r["disp"]))
+            st, res = B.pin_serve_wait(srv, t, 120.0)
+            assert st == B.PIN_OK, B.pin_last_error()
+            served.append(_served(lib, res, r))
+            B.pin_serve_release(srv, t)
+    finally:
+        B.pin_serve_destroy(srv)
+    torch.cuda.synchronize()
+    for r, got in zip(reqs, served):
+        for a, b in zip(got, _plain(lib, r)):
+            assert np.array_equal(a, b), f"box {r['box']} differs from the plain path"
+
+
 def test_small_budget_serialises_and_completes(lib):
     B = lib
     one = B.pin_serve_slot_bytes(B.make_serve_config(1e12), 64)
