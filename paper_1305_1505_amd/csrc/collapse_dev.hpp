@@ -17,9 +17,10 @@
 //   F = delta/delta_c and a plane F = lambda_1.
 //
 // Arithmetic: float64.  lambda_1 from the trigonometric closed form of a symmetric 3x3
-// eigenproblem, lambda_1 = m + 2p cos(acos(r)/3) with r = det(B)/(2p^3); near r = -1
-// (lambda_1 ~ lambda_2) that form amplifies the rounding of r by 1/sqrt(1+r), so there the
-// eigenvalue comes from cyclic Jacobi rotations instead.  The cubic's largest real root comes from
+// eigenproblem, lambda_1 = m + 2p cos(acos(r)/3) with r = det(B)/(2p^3), evaluated as a
+// polynomial in sqrt(1 + r) and polished by Newton steps on the characteristic polynomial; near
+// r = -1 (lambda_1 ~ lambda_2) the two largest roots nearly coincide, so there the eigenvalue
+// comes from cyclic Jacobi rotations instead.  The cubic's largest real root comes from
 // the closed form (trigonometric for three real roots, Cardano otherwise) polished by Newton
 // steps on P.
 #pragma once
@@ -46,11 +47,21 @@ __device__ __forceinline__ double cubic_largest_real_root(double a, double b, do
   const double disc = hq * hq + p3 * p3 * p3;
   double t;
   if (disc < 0.0) {
-    // three real roots (p < 0): t_k = 2 r cos(theta/3 - 2 pi k/3), cos(theta) = -hq / r^3
+    // three real roots (p < 0): t_k = 2 r cos(theta/3 - 2 pi k/3), cos(theta) = -hq / r^3; the
+    // largest from the polynomial in sqrt(1 + cos theta) (within 1.1e-8 of it; the Newton steps
+    // below polish it) unless the two largest roots nearly coincide
     const double r = sqrt(-p3);
     double cth = -hq / (r * r * r);
     cth = fmin(1.0, fmax(-1.0, cth));
-    t = 2.0 * r * cos(acos(cth) * (1.0 / 3.0));
+    if (cth > -1.0 + 1e-8) {
+      const double u = sqrt(1.0 + cth);
+      double cu = (double)kAcos3U[8];
+#pragma unroll
+      for (int k = 7; k >= 0; --k) cu = fma(cu, u, (double)kAcos3U[k]);
+      t = 2.0 * r * cu;
+    } else {
+      t = 2.0 * r * cos(acos(cth) * (1.0 / 3.0));
+    }
   } else {
     const double u = cbrt(-hq - copysign(sqrt(disc), hq));
     t = (u != 0.0) ? (u - p3 / u) : 0.0;
@@ -130,7 +141,21 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
     double r = detb / (2.0 * p2 * p);
     r = fmin(1.0, fmax(-1.0, r));
     if (r > -1.0 + 1e-8) {
-      l1 = m + 2.0 * p * cos(acos(r) * (1.0 / 3.0));
+      // c(r) = cos(arccos(r)/3) from its polynomial in sqrt(1 + r) (within 1.1e-8), then Newton
+      // steps on y^3 - 3 p^2 y - det B, whose largest root y = lambda_1 - m is simple here (the
+      // two largest roots are at least ~1e-4 p apart): from 2e-8 p two steps reach rounding
+      const double u = sqrt(1.0 + r);
+      double c = (double)kAcos3U[8];
+#pragma unroll
+      for (int k = 7; k >= 0; --k) c = fma(c, u, (double)kAcos3U[k]);
+      double y = 2.0 * p * c;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const double f = (y * y - 3.0 * p2) * y - detb;
+        const double fp = 3.0 * (y * y - p2);
+        if (fp > 0.0) y -= f / fp;
+      }
+      l1 = m + y;
     } else {
       l1 = jacobi_largest_eigenvalue(xx, xy, xz, yy, yz, zz);
     }
