@@ -71,7 +71,7 @@ __device__ __forceinline__ double cubic_largest_real_root(double a, double b, do
   for (int it = 0; it < 2; ++it) {
     const double f = ((x + a) * x + b) * x + c;
     const double fp = (3.0 * x + 2.0 * a) * x + b;
-    if (fp > 0.0) x -= f / fp;
+    if (fp > 0.0) x -= f * __builtin_amdgcn_rcp(fp);   // approximate reciprocal: the step is a correction
   }
   return x;
 }
@@ -153,7 +153,7 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
       for (int it = 0; it < 2; ++it) {
         const double f = (y * y - 3.0 * p2) * y - detb;
         const double fp = 3.0 * (y * y - p2);
-        if (fp > 0.0) y -= f / fp;
+        if (fp > 0.0) y -= f * __builtin_amdgcn_rcp(fp);
       }
       l1 = m + y;
     } else {
