@@ -5,7 +5,11 @@
 * planar collapse: the Zel'dovich solution is exact, F = lambda_1;
 * the sphere: F = delta/delta_c (the paper's statement for spherical collapse);
 * homogeneity of degree 1; the root finder against numpy.roots and a dense scan of J1(D);
-* lambda_1 against the closed trigonometric form; invariants against eigenvalues.
+* lambda_1 against the closed trigonometric form; invariants against eigenvalues;
+* each coefficient of the E3 cubic against the LPT oracles, which the equations of motion pin:
+  a = -lambda_1 of the Zel'dovich displacement gradient, b = div(psi2)/3 from the 2LPT
+  displacement, c = div(psi3)/3 from the 3LPT source with the second-order potential Hessian
+  taken isotropic (mu2/3 on each axis), i.e. every order shared equally by the three axes.
 """
 
 import functools
@@ -14,7 +18,7 @@ import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
 
-from oracle import collapse
+from oracle import collapse, hessian, lpt3, run
 
 
 @functools.lru_cache(maxsize=None)
@@ -176,21 +180,109 @@ def test_sphericity_limits():
     assert collapse.sphericity(np.array([-1.0]), np.array([0.0]))[0] == 0.0
 
 
+def _band_limited_field(seed, n=32, fmax=2):
+    """Half spectrum with |f_i| <= fmax only (no product of two fields reaches the Nyquist
+    frequency, so spectral derivatives of the LPT fields are exact), unit rms."""
+    rng = np.random.default_rng(seed)
+    fx, fy, fz = hessian.freq_grids(n)
+    keep = (np.abs(fx) <= fmax) & (np.abs(fy) <= fmax) & (fz <= fmax)
+    dk = (rng.standard_normal(keep.shape) + 1j * rng.standard_normal(keep.shape)) * keep
+    dk = np.fft.rfftn(np.fft.irfftn(dk, s=(n, n, n), axes=(0, 1, 2)), axes=(0, 1, 2))
+    dk[0, 0, 0] = 0.0
+    x = np.fft.irfftn(dk, s=(n, n, n), axes=(0, 1, 2))
+    return dk / np.sqrt(np.mean(x ** 2))
+
+
+def _spectral_gradient(psi, box):
+    """g[i][j] = d psi_i / d q_j of a periodic vector field (q in the units of box)."""
+    n = psi.shape[1]
+    f = hessian.freq_grids(n)
+    out = []
+    for i in range(3):
+        pk = np.fft.rfftn(psi[i], axes=(0, 1, 2))
+        out.append([np.fft.irfftn(1j * (2 * np.pi / box) * f[j] * pk, s=(n, n, n), axes=(0, 1, 2))
+                    for j in range(3)])
+    return out
+
+
+def _lpt_coefficient_residuals(coefficients, seed=12, box=100.0):
+    """Largest |residual| / scale of (a, b, c) from `coefficients` against the LPT oracles.
+
+    With the growing mode D as clock and every order >= 2 shared equally by the three axes, the
+    stretch of the first axis is J1(D) = 1 + D psi1_{1,1} + D^2 div(psi2)/3 + D^3 div(psi3)/3,
+    and F^3 J1(1/F) = F^3 + a F^2 + b F + c.  psi1_{1,1} along the first axis is minus the largest
+    eigenvalue of -grad(psi1) (the Zel'dovich displacement's gradient is -T); div(psi2) is taken
+    spectrally from the 2LPT displacement (whose k = 0 mode is removed, so both sides lose their
+    mean); div(psi3) is the 3LPT divergence source evaluated with T2 = (mu2/3) I.
+    """
+    dk = _band_limited_field(seed)
+    t1 = hessian.deformation_tensor(dk, None)
+    delta, mu2, mu3, p = collapse.invariants(t1)
+    l1 = collapse.largest_eigenvalue(t1)
+    a, b, c = coefficients(l1, delta, mu2, mu3)
+    g1 = _spectral_gradient(run.za_displacement(dk, box), box)
+    mt = -np.stack([np.stack([0.5 * (g1[i][j] + g1[j][i]) for j in range(3)], -1) for i in range(3)], -2)
+    a_lpt = -np.linalg.eigvalsh(mt)[..., 2]
+    g2 = _spectral_gradient(run.lpt2_displacement(dk, box), box)
+    div2 = g2[0][0] + g2[1][1] + g2[2][2]
+    m2 = lpt3.mu2(t1)
+    z = np.zeros_like(m2)
+    s3, _ = lpt3.third_order_sources(t1, [m2 / 3.0, z, z, m2 / 3.0, z, m2 / 3.0])
+    res_a = np.max(np.abs(a - a_lpt)) / np.max(np.abs(a_lpt))
+    res_b = np.max(np.abs((3.0 * b - np.mean(3.0 * b)) - div2)) / np.max(np.abs(div2))
+    res_c = np.max(np.abs(3.0 * c - s3)) / np.max(np.abs(s3))
+    return res_a, res_b, res_c
+
+
+def test_cubic_coefficients_are_the_lpt_traces():
+    res = _lpt_coefficient_residuals(collapse.cubic_coefficients)
+    assert max(res) <= 1e-12, res
+
+
+def test_cubic_constant_term_is_the_isotropic_3lpt_source_on_random_tensors():
+    t6 = _random_tensors(20000, 13)
+    delta, mu2, mu3, p = collapse.invariants(t6)
+    _, b, c = collapse.cubic_coefficients(collapse.largest_eigenvalue(t6), delta, mu2, mu3)
+    m2 = lpt3.mu2(t6)
+    z = np.zeros_like(m2)
+    s3, _ = lpt3.third_order_sources(t6, [m2 / 3.0, z, z, m2 / 3.0, z, m2 / 3.0])
+    assert np.max(np.abs(3.0 * c - s3)) <= 1e-14 * np.max(np.abs(s3))
+    # the isotropic second-order Hessian has trace mu2, the 2LPT potential's Laplacian
+    assert np.max(np.abs(mu2 - m2)) <= 1e-14 * np.max(np.abs(m2))
+
+
+def _true_plane(lam, seed):
+    return [np.array([v]) for v in _rot([lam, 0, 0, 0, 0, 0], seed)]
+
+
 def test_pins_catch_planted_mistakes(monkeypatch):
-    """Each plausible slip in the E3 cubic breaks the sphere or the plane pin above."""
+    """Each plausible slip in the E3 cubic fails a pin.  The sphere and the plane only fix the sum
+    of the higher-order weights at lambda_i = delta/3 and the first-order term; two slips pass
+    both (the anisotropic second-order split -(3/7) lambda_2 lambda_3, and a shift of weight
+    between mu3 and delta mu2 that keeps the sphere's sum), and the LPT-trace pin catches them."""
     good = collapse.cubic_coefficients
-    mistakes = [
+    sphere = _iso(np.array([1.3]))
+    plane = _true_plane(0.9, 4)
+    # old slips: each moves the sphere or the plane
+    visible = [
         lambda l1, d, m2, m3: (-l1, -m2 / 7, m3 / 9),                         # dropped delta mu2
         lambda l1, d, m2, m3: (-l1, +m2 / 7, m3 / 9 - 10 * d * m2 / 189),      # sign of mu2/7
         lambda l1, d, m2, m3: (-l1, -m2 / 7, m3 / 3 - 10 * d * m2 / 189),      # wrong mu3 weight
         lambda l1, d, m2, m3: (-d, -m2 / 7, m3 / 9 - 10 * d * m2 / 189),       # delta for lambda_1
     ]
-    sphere = _iso(np.array([1.3]))
-    plane = [np.array([v]) for v in _rot([0.9, 0, 0, 0.2, 0, 0], 4)]
-    plane_ok = collapse.inverse_collapse_time(plane)[0]
-    for bad in mistakes:
+    # slips the sphere and the plane cannot see
+    hidden = [
+        # -(3/7) lambda_2 lambda_3 on the first axis, with lambda_2 lambda_3 = mu2 - l1 (delta - l1)
+        lambda l1, d, m2, m3: (-l1, -(3.0 / 7.0) * (m2 - l1 * (d - l1)), m3 / 9 - 10 * d * m2 / 189),
+        # mu3/9 -> 2 mu3/9 with the delta mu2 weight moved to keep the sphere's sum
+        lambda l1, d, m2, m3: (-l1, -m2 / 7, 2 * m3 / 9 - (10.0 / 189 + 1.0 / 81) * d * m2),
+    ]
+    for bad in visible + hidden:
         monkeypatch.setattr(collapse, "cubic_coefficients", bad)
         f_s = collapse.inverse_collapse_time(sphere)[0]
         f_p = collapse.inverse_collapse_time(plane)[0]
-        assert abs(f_s - 1.3 / collapse.DELTA_C) > 1e-6 or abs(f_p - plane_ok) > 1e-6
+        moved = abs(f_s - 1.3 / collapse.DELTA_C) > 1e-6 or abs(f_p - 0.9) > 1e-6
+        assert moved == (bad in visible)
+        assert max(_lpt_coefficient_residuals(bad)) > 1e-2
     monkeypatch.setattr(collapse, "cubic_coefficients", good)
+    assert max(_lpt_coefficient_residuals(good)) <= 1e-12
