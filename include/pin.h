@@ -250,6 +250,21 @@ pin_status pin_fragment_mergers(pin_plan plan, double* f, int32_t* keep, int32_t
  * 1 - x/3 - x^2/21 - 23x^3/1701, delta_c = (3/20)(12 pi)^(2/3).  count = 0 is a no-op. */
 pin_status pin_inverse_collapse_time(pin_plan plan, const void* T6, size_t count, void* F, hipStream_t stream);
 
+/* pin_collapse_times for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no plan, no hipMalloc/hipFree,
+ * no copy from host memory and no host wait -- only kernel launches on `stream`.  The workspace a
+ * plan would allocate (11 half-spectrum slots, twiddle and window tables) is one static device
+ * array of 96 MiB that the library holds on each device it runs on until the process ends; its
+ * device address is looked up once per device on the first call there.  desc as for
+ * pin_plan_create (the spectrum fields are not used); dk, F and ridx as for pin_collapse_times
+ * (device, caller-owned), with the same results.  Sizes: N <= 128 in PIN_FP32 and N <= 96 in
+ * PIN_FP64 (any radius count); larger ones return PIN_ERR_UNSUPPORTED_SIZE before anything is
+ * queued.  Every call on a device shares that device's array: calls that overlap on one device
+ * (on different streams, or from different threads) race and give undefined results; calls
+ * ordered on one stream are safe.  Each call rewrites every part of the array it reads. */
+pin_status pin_collapse_times_noalloc(const pin_plan_desc* desc, const void* dk, void* F, uint8_t* ridx,
+                                      hipStream_t stream);
+
 /* Per-kernel timing with HIP events recorded around every launch of the plan on its stream.
  * Kernel classes are numbered 0..pin_kernel_class_count()-1 and named by pin_kernel_class_name. */
 int pin_kernel_class_count(void);

@@ -69,6 +69,7 @@ _sig = {
     "pin_collapse_reset": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pin_collapse_times_range": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "pin_collapse_times": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "pin_collapse_times_noalloc": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), _vp, _vp, _vp, _vp]),
     "pin_deformation_tensor": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "pin_plan_velocity_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pin_plan_desc), ctypes.POINTER(ctypes.c_size_t)]),
     "pin_collapse_reset_v": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -159,6 +160,10 @@ def pin_collapse_times_range(plan, dk, F, ridx, r_begin, r_end, stream=0):
 
 def pin_collapse_times(plan, dk, F, ridx, stream=0):
     _check(lib.pin_collapse_times(plan, _vp(dk), _vp(F), _vp(ridx), _vp(stream)))
+
+
+def pin_collapse_times_noalloc(desc, dk, F, ridx, stream=0):
+    _check(lib.pin_collapse_times_noalloc(ctypes.byref(desc), _vp(dk), _vp(F), _vp(ridx), _vp(stream)))
 
 
 def pin_plan_velocity_workspace_bytes(desc):

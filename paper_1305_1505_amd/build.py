@@ -51,6 +51,8 @@ def build(jobs=None, verbose=False):
     # fragmentation: float64 decisions in the order the method states them, no contraction
     tasks.append([HIPCC, *COMMON, "-ffp-contract=off", "-c", os.path.join(CSRC, "fragment.hip"),
                   "-o", os.path.join(BUILD, "fragment.o")])
+    # allocation-free collapse times: static device scratch and its table kernels
+    tasks.append([HIPCC, *COMMON, "-c", os.path.join(CSRC, "noalloc.hip"), "-o", os.path.join(BUILD, "noalloc.o")])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
         tasks.append([HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
