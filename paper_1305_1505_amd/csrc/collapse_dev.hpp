@@ -173,16 +173,14 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
 // ---------------------------------------------------------------------------------------------
 // Mixed-precision path of collapse_point for float32 tensor components.
 //
-// The products and sums that lose accuracy near degeneracy -- the invariants, det(B), and the
-// discriminants 4p^6 - det(B)^2 (= 4p^6 (1 - r^2)) and hq^2 + p3^3 of the depressed collapse
-// cubic -- are formed in float64 (full rate on gfx950, no transcendental functions).  From them
-// 1 + r and 1 + r_c are known to float32 relative accuracy even as r -> -1, so the remaining
-// square roots, cube roots and c(r) = cos(arccos(r)/3) run in float32 without the usual sqrt(eps)
-// loss at lambda_1 ~ lambda_2 or at a double root: c(r) = U(sqrt(1 + r)) is one polynomial over
-// all of [-1, 1] (trig_poly.hpp), so no lane branches on the sign of r.  lambda_1 and the collapse
-// root each get one float64 Newton step (on the characteristic polynomial of B = T - m I and on
-// P); the Newton step on lambda_1 is skipped where that polynomial is near a double root (there
-// the closed form is already accurate).
+// The invariants are formed in float64 from the float32 components (exact products), and so are
+// p = sqrt(p^2) and r = det(B)/(2 p^3), from one reciprocal square root: then 1 + r keeps float64
+// absolute accuracy as r -> -1 (lambda_1 -> lambda_2), where c(r) = cos(arccos(r)/3) is steepest,
+// and the same holds for the collapse cubic's 1 + r_c at a double root.  c is one float32
+// polynomial in sqrt(1 + r) over all of [-1, 1] (trig_poly.hpp), so no lane branches on the sign
+// of r.  With 1 + r accurate, the closed form gives lambda_1 to the polynomial's float32
+// evaluation (~1e-7 of p) with no polishing; the collapse root gets one float64 Newton step on P.
+// The cubic's coefficients are taken directly in depressed form (F = t + lambda_1/3).
 
 // c(r) = cos(arccos(r)/3) from opr = 1 + r.
 __device__ __forceinline__ float acos3_cos(float opr) {
@@ -201,14 +199,12 @@ __device__ __forceinline__ float fast_cbrt(float v) {
   return a == 0.f ? 0.f : copysignf(y, v);
 }
 
-// 1 + r for r in [-1, 1], given the float64 pair (num, den) with 1 - r^2 = num/den (num, den of
-// one sign).  For r < 0 it is (1 - r^2)/(1 - r), free of the cancellation in 1 + r; for r >= 0,
-// or if den is not representable in float32, plain 1 + r.
-__device__ __forceinline__ float one_plus_r(float r, double num, double den) {
-  const float dn = (float)den;
-  const float viaq = fmaxf(0.f, (float)num * __builtin_amdgcn_rcpf(dn * (1.f - r)));
-  const bool usable = r < 0.f && fabsf(dn) > 0.f && fabsf(dn) < 1.0e38f;
-  return usable ? viaq : 1.f + r;
+// 1/sqrt(x) for x > 0 in float64: the hardware estimate y and one Newton step y + y e / 2 with
+// the residual e = 1 - x y^2, which squares the estimate's relative error.
+__device__ __forceinline__ double rsq_f64(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
 }
 
 __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, float fxz, float fyy, float fyz,
@@ -218,55 +214,49 @@ __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, floa
   const double m = delta * (1.0 / 3.0);
   const double bxx = xx - m, byy = yy - m, bzz = zz - m;
   const double off = xy * xy + xz * xz + yz * yz;
-  const double p2 = (bxx * bxx + byy * byy + bzz * bzz + 2.0 * off) * (1.0 / 6.0);
+  const double s6 = bxx * bxx + byy * byy + bzz * bzz + 2.0 * off;   // tr(B^2) = 6 p^2
   const double detb = bxx * (byy * bzz - yz * yz) - xy * (xy * bzz - yz * xz) + xz * (xy * yz - byy * xz);
-  // invariants of T = B + m I from those of B (tr B = 0, mu2(B) = -3 p^2)
-  const double mu2 = 3.0 * (m * m - p2);
-  const double mu3 = m * (m * m - 3.0 * p2) + detb;
-  // lambda_1 = m + y, y = 2 p c(r) the largest root of y^3 - 3 p^2 y - det B, r = det B / (2 p^3);
-  // p = 0 (a sphere) gives r = 0 and lambda_1 = m
-  const float p2f = (float)p2;
-  const float p = __builtin_amdgcn_sqrtf(p2f);
-  const float rq = (float)detb * __builtin_amdgcn_rcpf(2.f * p2f * p);
-  const float r = p2f > 0.f ? fminf(1.f, fmaxf(-1.f, rq)) : 0.f;
-  const double p6 = 4.0 * p2 * p2 * p2;
-  double y = 2.0 * (double)p * (double)acos3_cos(one_plus_r(r, p6 - detb * detb, p6));
-  {
-    const double ch = (y * y - 3.0 * p2) * y - detb;
-    const double chp = 3.0 * (y * y - p2);
-    const double step = ch * (double)__builtin_amdgcn_rcpf((float)chp);
-    y = chp > 1e-6 * p2 ? y - step : y;
-  }
+  // invariants of T = B + m I from those of B (tr B = 0, mu2(B) = -3 p^2): mu2 = 3 m^2 - 3 p^2,
+  // mu3 = m (m^2 - 3 p^2) + det B
+  const double h3 = 0.5 * s6;
+  const double mu2 = delta * m - h3;
+  const double mu3 = m * (m * m - h3) + detb;
+  // lambda_1 = m + y, y = 2 p c(r) the largest root of y^3 - 3 p^2 y - det B, with
+  // r = det B / (2 p^3) = det B (6/tr B^2)^(3/2) / 2; tr B^2 = 0 (a sphere, det B = 0 too) gives
+  // p = 0 and r = 0 through the floor
+  const double qs = rsq_f64(fmax(s6, 1e-200));
+  const double r = detb * (qs * qs * qs) * 7.3484692283495345;      // 6^(3/2) / 2
+  const double y = s6 * qs * (2.0 / 2.4494897427831781) * (double)acos3_cos((float)(1.0 + r));
   const double l1 = m + y;
-  // collapse cubic P(F) = F^3 + a F^2 + b F + c, depressed with F = t - a/3
-  const double a = -l1;
-  const double b = -mu2 * (1.0 / 7.0);
-  const double c = mu3 * (1.0 / 9.0) - 10.0 * delta * mu2 * (1.0 / 189.0);
-  const double a3 = a * (1.0 / 3.0);
-  const double hq = 0.5 * (c - a3 * b + 2.0 * a3 * a3 * a3);
-  const double p3 = (b - a * a3) * (1.0 / 3.0);
-  const double p3c = p3 * p3 * p3;
-  const double disc = hq * hq + p3c;
-  float t;
+  // collapse cubic P(F) = F^3 - l1 F^2 - (mu2/7) F + c0, c0 = mu3/9 - 10 delta mu2/189; with
+  // F = t + l1/3 it is t^3 + 3 p3 t + 2 hq, p3 = -(mu2/21 + l1^2/9), hq = c0/2 - l1 (mu2/42 + l1^2/27)
+  const double l1s = l1 * l1;
+  const double c0 = mu3 * (1.0 / 9.0) - (delta * mu2) * (10.0 / 189.0);
+  const double p3 = -(mu2 * (1.0 / 21.0) + l1s * (1.0 / 9.0));
+  const double hq = 0.5 * c0 - l1 * (mu2 * (1.0 / 42.0) + l1s * (1.0 / 27.0));
+  const double disc = hq * hq + p3 * p3 * p3;
+  double t;
   if (disc < 0.0) {
-    // three real roots: t = 2 sqrt(-p3) c(r_c), r_c = -hq / (-p3)^(3/2), 1 - r_c^2 = disc / p3^3
-    const float rr = __builtin_amdgcn_sqrtf((float)(-p3));
-    const float rc = fminf(1.f, fmaxf(-1.f, (float)(-hq) * __builtin_amdgcn_rcpf(rr * rr * rr)));
-    t = 2.f * rr * acos3_cos(one_plus_r(rc, disc, p3c));
+    // three real roots (p3 < 0): t = 2 sqrt(-p3) c(r_c), r_c = -hq / (-p3)^(3/2)
+    const double qc = rsq_f64(-p3);
+    const double rc = -hq * (qc * qc * qc);
+    t = 2.0 * (-p3 * qc) * (double)acos3_cos((float)(1.0 + rc));
   } else {
     const float sd = __builtin_amdgcn_sqrtf((float)disc);
     const float u = fast_cbrt((float)(-hq) - copysignf(sd, (float)hq));
-    t = u != 0.f ? u - (float)p3 * __builtin_amdgcn_rcpf(u) : 0.f;
+    t = u != 0.f ? (double)(u - (float)p3 * __builtin_amdgcn_rcpf(u)) : 0.0;
   }
-  double x = (double)t - a3;
+  // one float64 Newton step on P
+  const double b = mu2 * (-1.0 / 7.0);
+  double x = t + l1 * (1.0 / 3.0);
   {
-    const double f = ((x + a) * x + b) * x + c;
-    const double fp = (3.0 * x + 2.0 * a) * x + b;
-    const double step = f * (double)__builtin_amdgcn_rcpf((float)fp);
-    x = fp > 0.0 ? x - step : x;
+    const double f = ((x - l1) * x + b) * x + c0;
+    const double fp = (3.0 * x - 2.0 * l1) * x + b;
+    x = fp > 0.0 ? x - f * __builtin_amdgcn_rcp(fp) : x;   // approximate reciprocal: a correction
   }
   const float fe3 = x > 0.0 ? (float)x : 0.f;
   const float dl = (float)delta;
+  const float p = (float)(s6 * qs * (1.0 / 2.4494897427831781));
   const float s = dl > 0.f ? fminf(1.f, fmaxf(0.f, 1.f - 3.f * p * __builtin_amdgcn_rcpf(dl))) : 0.f;
   return fe3 * (1.f + sphere_gain * s);
 }
