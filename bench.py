@@ -74,29 +74,74 @@ def measured_issue(cls, n, prec):
     return t["kernels"][cls]["valu_issue_ns"]
 
 
-def cpu_baseline(sample_n=64, radius_stride=1):
-    """The FP64 oracle on a bounded sample of the workload: a sample_n^3 grid with the same cell
-    size (box scaled), every radius_stride-th radius, full step (field, collapse, displacements)."""
+def cpu_baseline(sample_n=256, workers=None):
+    """The FP64 oracle, as it stands, timed on the host cores on a bounded sample of the workload.
+
+    Sample: a sample_n^3 grid at the workload's cell size (box scaled), the field, the first and
+    the last of its radii (their deformation tensors in two threads; the per-point collapse step
+    over chunks of points in a thread pool -- NumPy releases the GIL in its FFTs, LAPACK calls and
+    array arithmetic), and the ZA and 2LPT displacements (two threads).  The time of the full step
+    is extrapolated linearly in the radius count: field + n_radii x (time per radius) +
+    displacements.  cores = the threads busy on average (process CPU time / wall time)."""
+    import concurrent.futures as cf
+
     import numpy as np
 
+    from oracle import collapse, field, hessian, run
+    from paper_1305_1505_amd import workloads as W
+
+    cfg = W.CONFIGS["c512_fp32"]
+    box = cfg["box"] * sample_n / cfg["n"]
+    radii = W.config_radii(cfg)
+    sample_radii = [radii[0], radii[-1]]
+    workers = workers or min(16, os.cpu_count() or 1)
+    n3 = sample_n ** 3
+    chunk = -(-n3 // (4 * workers))
+    with cf.ThreadPoolExecutor(workers) as pool:
+        t0, c0 = time.perf_counter(), time.process_time()
+        dk = field.linear_field(cfg["seed"], sample_n, box, W.SIGMA8, W.GAMMA, W.NS)
+        t1 = time.perf_counter()
+        tens = list(pool.map(lambda r: [c.ravel() for c in hessian.deformation_tensor(dk, r)], sample_radii))
+        fmax = np.zeros(n3)
+        ridx = np.full(n3, run.NEVER, dtype=np.uint8)
+        for k, t6 in enumerate(tens):
+            f = np.concatenate(list(pool.map(
+                lambda s: collapse.inverse_collapse_time([c[s:s + chunk] for c in t6]), range(0, n3, chunk))))
+            up = f > fmax
+            fmax = np.where(up, f, fmax)
+            ridx = np.where(up, np.uint8(k), ridx)
+        del tens
+        t2 = time.perf_counter()
+        list(pool.map(lambda fn: fn(dk, box), (run.za_displacement, run.lpt2_displacement)))
+        t3 = time.perf_counter()
+        cpu = time.process_time() - c0
+    per_radius = (t2 - t1) / len(sample_radii)
+    total = (t1 - t0) + len(radii) * per_radius + (t3 - t2)
+    return {"value": n3 * len(radii) / total, "unit": "updates/s", "cores": round(cpu / (t3 - t0), 1),
+            "kind": "oracle", "measured_s": round(t3 - t0, 2), "extrapolated_step_s": round(total, 1),
+            "per_radius_s": round(per_radius, 2), "field_s": round(t1 - t0, 2), "displacements_s": round(t3 - t2, 2),
+            "sample": f"{sample_n}^3 grid at the workload's cell size ({box:g} Mpc/h): field, the first and last "
+                      f"of its {len(radii)} radii (deformation tensors, collapse, running maximum), ZA + 2LPT; "
+                      f"step time extrapolated linearly to {len(radii)} radii; float64 NumPy/SciPy oracle, "
+                      f"{workers} threads, {os.cpu_count()} host cores visible ({_cpu_model()})"}
+
+
+def cpu_baseline_single(sample_n=64):
+    """The oracle on one thread on a small grid at the workload's cell size, every radius (the
+    figure reported before the threaded sample; kept as a secondary field)."""
     from oracle import field, run
     from paper_1305_1505_amd import workloads as W
 
     cfg = W.CONFIGS["c512_fp32"]
     box = cfg["box"] * sample_n / cfg["n"]
-    radii = W.config_radii(cfg)[::radius_stride]
-    t0, c0 = time.perf_counter(), time.process_time()
+    radii = W.config_radii(cfg)
+    t0 = time.perf_counter()
     dk = field.linear_field(cfg["seed"], sample_n, box, W.SIGMA8, W.GAMMA, W.NS)
     run.collapse_times(dk, radii)
     run.displacements(dk, box)
-    dt, cpu = time.perf_counter() - t0, time.process_time() - c0
-    updates = sample_n ** 3 * len(radii)
-    cores = max(1, int(round(cpu / dt)))          # threads actually busy on average
-    return {"value": updates / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"{sample_n}^3 grid at the workload's cell size ({box:g} Mpc/h), "
-                      f"{len(radii)} of its {cfg['n_radii']} radii, field + collapse + ZA/2LPT, "
-                      f"float64 NumPy/SciPy, {os.cpu_count()} host cores visible ({_cpu_model()})"}
+    dt = time.perf_counter() - t0
+    return {"value": sample_n ** 3 * len(radii) / dt, "unit": "updates/s", "cores": 1, "seconds": round(dt, 2),
+            "sample": f"{sample_n}^3 grid ({box:g} Mpc/h), all {len(radii)} radii, field + collapse + ZA/2LPT"}
 
 
 def _cpu_model():
@@ -164,10 +209,13 @@ def serve_bench(B, W, full=False):
 
     run(trace[:warm], paced=True)
     measured = trace[warm:]
+    print(f"[bench] serving: {warm} warm-up requests done; {len(measured)} paced at "
+          f"{W.SERVE['rate_per_s']:g}/s", file=sys.stderr, flush=True)
     updates = sum(r["n"] ** 3 * len(r["radii"]) for r in measured)
     B.pin_serve_reset_stats(srv)
     wall_paced = run(measured, paced=True)
     paced = B.pin_serve_stats(srv)
+    print(f"[bench] serving: paced trace done in {wall_paced:.1f} s; saturated replay", file=sys.stderr, flush=True)
     B.pin_serve_reset_stats(srv)
     wall_sat = run(measured, paced=False)
     sat = B.pin_serve_stats(srv)
@@ -209,7 +257,8 @@ def serve_bench(B, W, full=False):
     served_rate = updates / wall_sat
     plain_rate = updates / wall_plain
     return {
-        "requests": len(measured), "warmup": warm, "rate_per_s": W.SERVE["rate_per_s"],
+        "requests": len(measured), "warmup": warm, "latency_samples": int(paced["completed"]),
+        "rate_per_s": W.SERVE["rate_per_s"],
         "sizes": list(W.SERVE["sizes"]), "budget_bytes": W.SERVE["hbm_budget"],
         "p50_latency_s": round(paced["p50_s"], 4), "p99_latency_s": round(paced["p99_s"], 4),
         "mean_latency_s": round(paced["mean_s"], 4), "paced_wall_s": round(wall_paced, 2),
@@ -218,6 +267,70 @@ def serve_bench(B, W, full=False):
         "saturated_p99_latency_s": round(sat["p99_s"], 4),
         "note": "plain = the same requests one after another through pin_* on one plan per grid size",
     }
+
+
+def kernel_times(B, plan, fn, repeats):
+    """{class name: total_ms, launches, avg_ms} over `repeats` calls of fn with per-launch events."""
+    import torch
+
+    B.pin_plan_set_timing(plan.handle, True)
+    for _ in range(repeats):
+        fn()
+    torch.cuda.synchronize()
+    out = {}
+    for c in range(B.pin_kernel_class_count()):
+        ms, cnt = B.pin_plan_kernel_time(plan.handle, c)
+        if cnt:
+            out[B.pin_kernel_class_name(c)] = {"total_ms": ms, "launches": cnt, "avg_ms": ms / cnt}
+    B.pin_plan_set_timing(plan.handle, False)
+    return out
+
+
+def config_leg(B, W, name):
+    """Collapse times alone on another workload: median of 5 after 2 warm-ups (HIP events on the
+    plan's stream), then one call with per-launch events for the three passes' durations and
+    their algorithmic GB/s."""
+    import torch
+
+    cfg = W.CONFIGS[name]
+    n, box = cfg["n"], cfg["box"]
+    radii = W.config_radii(cfg)
+    prec = B.PIN_FP64 if cfg["prec"] == "fp64" else B.PIN_FP32
+    plan = B.Plan(n, box, radii, W.SIGMA8, W.GAMMA, W.NS, prec)
+    real_bytes = 8 if prec == B.PIN_FP64 else 4
+    dk = plan.generate_field(cfg["seed"])
+    F = torch.empty((n, n, n), dtype=plan.real, device="cuda")
+    R = torch.empty((n, n, n), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def collapse():
+        B.pin_collapse_times(plan.handle, dk.data_ptr(), F.data_ptr(), R.data_ptr(), stream)
+
+    for _ in range(2):
+        collapse()
+    runs = []
+    for _ in range(5):
+        ev0.record()
+        collapse()
+        ev1.record()
+        torch.cuda.synchronize()
+        runs.append(ev0.elapsed_time(ev1))
+    ms = sorted(runs)[2]
+    kt = kernel_times(B, plan, collapse, 1)
+    passes = {}
+    for k in ("xpass_hessian", "ypass_hessian", "zpass_collapse"):
+        by = algorithmic_bytes(k, n, real_bytes)
+        gbs = by / (kt[k]["avg_ms"] * 1e-3) / 1e9
+        passes[k] = {"avg_ms": round(kt[k]["avg_ms"], 4), "bytes_per_launch": by, "GB/s": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del dk, F, R
+    plan.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"{n}^3 grid, {box:g} Mpc/h, {len(radii)} radii {cfg['r_max']:g}->{cfg['r_min']:g} cells, "
+                        f"collapse times only", "precision": cfg["prec"], "collapse_ms": round(ms, 2),
+            "updates_per_s": n ** 3 * len(radii) / (ms * 1e-3), "runs_ms": [round(x, 2) for x in runs],
+            "passes": passes}
 
 
 def main():
@@ -229,7 +342,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-full", action="store_true", help="full serving trace (20 + 300 requests)")
+    ap.add_argument("--serve-quick", action="store_true",
+                    help="short serving trace (10 + 60 requests) instead of the full 20 + 300")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 256^3 and 768^3 collapse legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three plain 1 GiB device copies (HBM counter calibration)")
     args = ap.parse_args()
@@ -267,7 +382,6 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warmup done: {args.config} N={n} radii={len(radii)}", file=sys.stderr, flush=True)
 
-    B.pin_plan_set_timing(plan.handle, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -277,14 +391,11 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     updates = n ** 3 * len(radii)
     value = updates / (elapsed / args.steps)
-
-    kernels = {}
-    for c in range(B.pin_kernel_class_count()):
-        ms, cnt = B.pin_plan_kernel_time(plan.handle, c)
-        if cnt:
-            kernels[B.pin_kernel_class_name(c)] = {"total_ms": ms, "launches": cnt, "avg_ms": ms / cnt}
-    B.pin_plan_set_timing(plan.handle, False)
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # per-kernel durations: HIP events around every launch, on the stream the kernels run on, in
+    # steps of their own after the timed region (the events stay out of ms_per_step)
+    kernels = kernel_times(B, plan, step, max(1, min(args.steps, 3)))
 
     # the dominant kernel of the path: largest summed time among the three per-radius passes
     dom = max(("xpass_hessian", "ypass_hessian", "zpass_collapse"), key=lambda k: kernels[k]["total_ms"])
@@ -399,10 +510,17 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    configs = None
+    if not args.no_configs and args.config == "c512_fp32":
+        configs = {}
+        for name in ("c256_fp32", "c768_fp32"):
+            configs[name] = config_leg(B, W, name)
+            print(f"[bench] {name}: collapse {configs[name]['collapse_ms']} ms", file=sys.stderr, flush=True)
+
     serve_out = None
     if not args.no_serve and args.config == "c512_fp32":
         print("[bench] serving leg", file=sys.stderr, flush=True)
-        serve_out = serve_bench(B, W, full=args.serve_full)
+        serve_out = serve_bench(B, W, full=not args.serve_quick)
         print(f"[bench] serving: p99 {serve_out['p99_latency_s']} s, served/plain "
               f"{serve_out['served_over_plain']}", file=sys.stderr, flush=True)
 
@@ -410,6 +528,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         base = cpu_baseline()
+        base["single_thread_64"] = cpu_baseline_single()
 
     out = {
         "metric": "grid-point x radius collapse updates/s at 512^3 (FP32 vs FP64); p99 serve latency",
@@ -438,6 +557,7 @@ def main():
         "fp64": fp64,
         "roofline": roofline,
         "kernels": per_kernel,
+        "configs": configs,
         "serve": serve_out,
         "cpu_baseline": base,
     }

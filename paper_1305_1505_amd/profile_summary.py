@@ -4,6 +4,7 @@
     python -m paper_1305_1505_amd.profile_summary traffic <fetch counter_collection.csv>
                                                          <write counter_collection.csv> <out.json> [out.md]
     python -m paper_1305_1505_amd.profile_summary issue <SQ counter_collection.csv> <out.json> [out.md]
+    (--n=<N> anywhere: the passes of grid size N instead of 512)
 
 `trace` turns a `rocprofv3 --kernel-trace --stats --output-format csv` kernel-stats file into a
 markdown table.  `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
@@ -28,12 +29,18 @@ KERNEL_SOURCES = ("kernels.hpp", "fft_core.hpp", "collapse_dev.hpp", "trig_poly.
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 3 << 30          # bench.py --copy-probe copies 2^28 float32 (1 GiB) three times
 
-# kernel-class name used by bench.py -> substring of the kernel name at N = 512, float32
-KERNEL_KEYS = {
-    "xpass_hessian": "k_xpass<float, 512, 0>",
-    "ypass_hessian": "k_ypass_packed<float, 512, 0>",
-    "zpass_collapse": "k_zpass<float, 512, 3, 0>",
+# kernel-class name used by bench.py -> substring of the kernel name at grid size N, float32
+KERNEL_PATTERNS = {
+    "xpass_hessian": "k_xpass<float, {n}, 0>",
+    "ypass_hessian": "k_ypass_packed<float, {n}, 0>",
+    "zpass_collapse": "k_zpass<float, {n}, 3, 0>",
 }
+KERNEL_KEYS = {k: v.format(n=512) for k, v in KERNEL_PATTERNS.items()}
+
+
+def set_grid_size(n):
+    """Summarise the passes of grid size n (default 512)."""
+    KERNEL_KEYS.update({k: v.format(n=n) for k, v in KERNEL_PATTERNS.items()})
 
 
 def kernel_source_hash():
@@ -152,6 +159,9 @@ def trace_table(stats_csv):
 
 
 def main(argv):
+    for a in [a for a in argv if a.startswith("--n=")]:
+        set_grid_size(int(a[4:]))
+        argv = [x for x in argv if x != a]
     if len(argv) >= 2 and argv[0] == "trace":
         table = trace_table(argv[1])
         if len(argv) > 2:
