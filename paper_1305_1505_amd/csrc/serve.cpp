@@ -21,13 +21,17 @@ struct HipSlot {
   uint8_t* ridx = nullptr;
   void* psi1 = nullptr;
   void* psi2 = nullptr;
-  std::map<std::tuple<int, double, int>, hipGraphExec_t> graphs;   // (n_radii, box, want_disp)
+  // captured graphs by (n_radii, box, want_disp), with the launch count of their last use; at
+  // most kMaxGraphs, the least recently used dropped first
+  std::map<std::tuple<int, double, int>, std::pair<hipGraphExec_t, uint64_t>> graphs;
+  uint64_t launches = 0;
 };
 
 class HipExec {
  public:
   using Slot = HipSlot;
   static constexpr int kMaxRadii = 254;
+  static constexpr size_t kMaxGraphs = 16;
 
   explicit HipExec(const pin_serve_config& c) : cfg_(c) {}
 
@@ -77,7 +81,7 @@ class HipExec {
     if (s == nullptr) return;
     (void)hipSetDevice(cfg_.device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second.first);
     for (void* p : {s->dk, s->F, (void*)s->ridx, s->psi1, s->psi2})
       if (p) (void)hipFree(p);
     if (s->done) (void)hipEventDestroy(s->done);
@@ -94,8 +98,19 @@ class HipExec {
     plan_generate_field(p, seed, s->dk, s->stream);
     const auto key = std::make_tuple((int)radii.size(), box, want_disp);
     auto it = s->graphs.find(key);
-    if (it == s->graphs.end()) it = s->graphs.emplace(key, capture(s, want_disp)).first;
-    hip_check(hipGraphLaunch(it->second, s->stream), "hipGraphLaunch");
+    if (it == s->graphs.end()) {
+      if (s->graphs.size() >= kMaxGraphs) {
+        // the slot is idle (its previous request completed), so no graph of it is in flight
+        auto old = s->graphs.begin();
+        for (auto g = s->graphs.begin(); g != s->graphs.end(); ++g)
+          if (g->second.second < old->second.second) old = g;
+        (void)hipGraphExecDestroy(old->second.first);
+        s->graphs.erase(old);
+      }
+      it = s->graphs.emplace(key, std::make_pair(capture(s, want_disp), uint64_t(0))).first;
+    }
+    it->second.second = ++s->launches;
+    hip_check(hipGraphLaunch(it->second.first, s->stream), "hipGraphLaunch");
     hip_check(hipEventRecord(s->done, s->stream), "hipEventRecord");
   }
 

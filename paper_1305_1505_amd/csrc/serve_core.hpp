@@ -311,7 +311,47 @@ class Core {
     return idx;
   }
 
-  bool admit_locked() {
+  struct Launch {
+    int slot;
+    uint64_t ticket;
+    Slot* h;
+    uint64_t seed;
+    double box;
+    std::vector<double> radii;
+    int want_disp;
+  };
+
+  // Admission: requests are matched to slots under the lock; their launches (radius tables,
+  // field, graph capture on a slot's first request of a shape, graph replay) run after it is
+  // released, so client calls never wait behind them.  Only this thread creates, launches and
+  // destroys slots, and a slot being launched is busy with a RUNNING request, so nothing else
+  // touches it meanwhile.
+  bool admit(std::unique_lock<std::mutex>& lk) {
+    std::vector<Launch> todo;
+    const bool progressed = admit_locked(todo);
+    if (todo.empty()) return progressed;
+    lk.unlock();
+    std::vector<std::pair<size_t, PinError>> failed;
+    for (size_t i = 0; i < todo.size(); ++i) {
+      const Launch& l = todo[i];
+      try {
+        exec_.launch(l.h, l.seed, l.box, l.radii, l.want_disp);
+      } catch (const PinError& e) {
+        failed.emplace_back(i, e);
+      }
+    }
+    lk.lock();
+    for (auto& f : failed) {
+      const Launch& l = todo[f.first];
+      Request& q = reqs_[l.ticket];
+      finish_locked(q, Request::FAILED, f.second.status, f.second.msg);
+      destroy_slot_locked(l.slot);
+      q.slot = -1;
+    }
+    return true;
+  }
+
+  bool admit_locked(std::vector<Launch>& todo) {
     bool progressed = false;
     std::vector<int> blocked;   // size classes whose head request could not be admitted
     for (auto it = queue_.begin(); it != queue_.end();) {
@@ -344,14 +384,8 @@ class Core {
       slots_[s].ticket = q.ticket;
       q.slot = s;
       q.t_admit = now();
-      try {
-        exec_.launch(slots_[s].h, q.seed, q.box, q.radii, q.want_disp);
-        q.state = Request::RUNNING;
-      } catch (const PinError& e) {
-        finish_locked(q, Request::FAILED, e.status, e.msg);
-        destroy_slot_locked(s);
-        q.slot = -1;
-      }
+      q.state = Request::RUNNING;
+      todo.push_back(Launch{s, q.ticket, slots_[s].h, q.seed, q.box, q.radii, q.want_disp});
       it = queue_.erase(it);
       progressed = true;
     }
@@ -395,7 +429,7 @@ class Core {
     std::unique_lock<std::mutex> lk(m_);
     for (;;) {
       poll_running_locked();
-      if (!stopping_) admit_locked();
+      if (!stopping_) admit(lk);
       const bool running = std::any_of(reqs_.begin(), reqs_.end(),
                                        [](const auto& kv) { return kv.second.state == Request::RUNNING; });
       if (stopping_ && !running) break;
