@@ -60,13 +60,14 @@ def smoothed_potential_spectrum(dk, radius_cells=None):
     return g
 
 
-def deformation_tensor(dk, radius_cells=None):
-    """The six components (xx, xy, xz, yy, yz, zz) of T_ij(x), each a real (N, N, N) array."""
+def deformation_tensor(dk, radius_cells=None, components=COMPONENTS):
+    """The components (a, b) of T_ij(x), each a real (N, N, N) array; by default all six
+    (xx, xy, xz, yy, yz, zz).  A subset gives the same arrays, for grids where six do not fit."""
     n = dk.shape[0]
     g = smoothed_potential_spectrum(dk, radius_cells)
     f = freq_grids(n)
     out = []
-    for a, b in COMPONENTS:
+    for a, b in components:
         out.append(np.fft.irfftn(f[a] * f[b] * g, s=(n, n, n), axes=(0, 1, 2)))
     return out
 

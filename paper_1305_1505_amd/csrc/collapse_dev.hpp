@@ -19,8 +19,9 @@
 // Arithmetic: float64.  lambda_1 from the trigonometric closed form of a symmetric 3x3
 // eigenproblem, lambda_1 = m + 2p cos(acos(r)/3) with r = det(B)/(2p^3), evaluated as a
 // polynomial in sqrt(1 + r) and polished by Newton steps on the characteristic polynomial; near
-// r = -1 (lambda_1 ~ lambda_2) the two largest roots nearly coincide, so there the eigenvalue
-// comes from cyclic Jacobi rotations instead.  The cubic's largest real root comes from
+// r = -1 (1 + r <= 1e-5, lambda_1 ~ lambda_2) the two largest roots nearly coincide and the
+// polynomial's root is ill-conditioned in its coefficients, so there the eigenvalue comes from
+// cyclic Jacobi rotations instead.  The cubic's largest real root comes from
 // the closed form (trigonometric for three real roots, Cardano otherwise) polished by Newton
 // steps on P.
 #pragma once
@@ -140,10 +141,12 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
     const double detb = bxx * (byy * bzz - yz * yz) - xy * (xy * bzz - yz * xz) + xz * (xy * yz - byy * xz);
     double r = detb / (2.0 * p2 * p);
     r = fmin(1.0, fmax(-1.0, r));
-    if (r > -1.0 + 1e-8) {
+    if (r > -1.0 + 1e-5) {
       // c(r) = cos(arccos(r)/3) from its polynomial in sqrt(1 + r) (within 1.1e-8), then Newton
       // steps on y^3 - 3 p^2 y - det B, whose largest root y = lambda_1 - m is simple here (the
-      // two largest roots are at least ~1e-4 p apart): from 2e-8 p two steps reach rounding
+      // two largest roots are at least ~5e-3 p apart): from 2e-8 p two steps reach the root of
+      // the computed polynomial, which the rounding of p^2 and det B moves by ~1e-16 p / sqrt(1 + r)
+      // (3e-14 p at the switch; closer to r = -1 the rotations below are backward stable)
       const double u = sqrt(1.0 + r);
       double c = (double)kAcos3U[8];
 #pragma unroll
@@ -178,9 +181,9 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
 // absolute accuracy as r -> -1 (lambda_1 -> lambda_2), where c(r) = cos(arccos(r)/3) is steepest,
 // and the same holds for the collapse cubic's 1 + r_c at a double root.  c is one float32
 // polynomial in sqrt(1 + r) over all of [-1, 1] (trig_poly.hpp), so no lane branches on the sign
-// of r.  With 1 + r accurate, the closed form gives lambda_1 to the polynomial's float32
-// evaluation (~1e-7 of p) with no polishing; the collapse root gets one float64 Newton step on P.
-// The cubic's coefficients are taken directly in depressed form (F = t + lambda_1/3).
+// of r.  With 1 + r and 1 + r_c accurate, the closed forms give lambda_1 and the collapse root to
+// the polynomial's float32 evaluation (~1e-7 of p and of the root) with no polishing.  The
+// cubic's coefficients are taken directly in depressed form (F = t + lambda_1/3).
 
 // c(r) = cos(arccos(r)/3) from opr = 1 + r.
 __device__ __forceinline__ float acos3_cos(float opr) {
@@ -246,14 +249,7 @@ __device__ __forceinline__ float collapse_point_mixed(float fxx, float fxy, floa
     const float u = fast_cbrt((float)(-hq) - copysignf(sd, (float)hq));
     t = u != 0.f ? (double)(u - (float)p3 * __builtin_amdgcn_rcpf(u)) : 0.0;
   }
-  // one float64 Newton step on P
-  const double b = mu2 * (-1.0 / 7.0);
-  double x = t + l1 * (1.0 / 3.0);
-  {
-    const double f = ((x - l1) * x + b) * x + c0;
-    const double fp = (3.0 * x - 2.0 * l1) * x + b;
-    x = fp > 0.0 ? x - f * __builtin_amdgcn_rcp(fp) : x;   // approximate reciprocal: a correction
-  }
+  const double x = t + l1 * (1.0 / 3.0);
   const float fe3 = x > 0.0 ? (float)x : 0.f;
   const float dl = (float)delta;
   const float p = (float)(s6 * qs * (1.0 / 2.4494897427831781));

@@ -31,6 +31,10 @@ CONFIGS = {
     "c512_fp64": dict(n=512, box=1000.0, n_radii=40, r_max=60.0, r_min=0.75, prec="fp64", seed=103),
     # 768^3 in 3072 Mpc/h, 45 radii 60 -> 0.75 cells, float32 FFTs (radix-3 sizes).
     "c768_fp32": dict(n=768, box=3072.0, n_radii=45, r_max=60.0, r_min=0.75, prec="fp32", seed=104),
+    # serving-trace grid sizes with their own radix-3 factorisations (2 Mpc/h per cell, 32 radii),
+    # float32 FFTs: parity cases
+    "s192_fp32": dict(n=192, box=384.0, n_radii=32, r_max=60.0, r_min=0.75, prec="fp32", seed=105),
+    "s384_fp32": dict(n=384, box=768.0, n_radii=32, r_max=60.0, r_min=0.75, prec="fp32", seed=106),
 }
 
 #: Serving trace: Poisson arrivals, grid sizes, 2 Mpc/h per cell, 24..40 radii, HBM budget.

@@ -1,22 +1,30 @@
 """Accuracy of the HIP path against the FP64 oracle on every workload: max and RMS relative error
-of F_max and of the ZA, 2LPT and 3LPT displacements, and the fraction of grid points whose collapse
-radius R_max differs (float32 and float64 plans).
+of F_max and of the ZA, 2LPT and 3LPT displacements, and the fraction of grid points whose
+collapse radius R_max differs (float32 and float64 plans).
 
-    python tests/accuracy_report.py [--workers 16] [--out report.json]
+Two phases, so that the oracle's hours of host work need no GPU and the GPU's output fits a
+bounded transfer:
 
-Full grids where the oracle fits the run time (64^3, 256^3; displacements, 3LPT included, also at
-512^3);
-sampled grid points (oracle.points) for F at 512^3 and 768^3 and psi1 at 768^3.  The oracle runs
-in a pool of worker processes started before this process touches the GPU; radii are split
-between workers and their partial maxima merged with the rule of the running maximum (larger F
-wins, a tie keeps the larger radius).  Metrics as in oracle.metrics: rel_rms = |x - x_o| / |x_o|,
-rel_max = max|x - x_o| / max|x_o|, mismatch = fraction of points with a different R_max.
-Prints one line per result as it arrives and a markdown table at the end.
+    python tests/accuracy_report.py gpu <out.npz> [--cases A,B,...]      # on the GPU
+    python tests/accuracy_report.py oracle <gpu.npz> <out.json> [--md out.md] [--threads 6]
+
+The GPU phase runs each case through the C ABI in the launch configuration bench.py uses (one
+plan, pin_generate_field, pin_collapse_times, pin_displacements, pin_lpt3_displacement) and keeps
+the outputs on a lattice of grid points: every `stride`-th point along each axis (stride 1 = the
+whole grid), one lattice for F_max and R_max and a coarser one for the displacements.  The oracle
+phase computes the same quantities on the whole grid from the oracle (field, deformation tensors
+per radius, collapse model, running maximum, displacements) and reads them at the same lattice
+points; nothing in it comes from the GPU.  The 768^3 case runs five of its radii (the first, the
+last and three between) on both sides: its full-grid tensors (six 3.6 GB float64 fields per
+radius) are the oracle's bottleneck.
+
+Metrics as in oracle.metrics, over the lattice points: rel_rms = |x - x_o| / |x_o|,
+rel_max = max|x - x_o| / max|x_o|, R mismatch = fraction of points whose R_max index differs.
 """
 
 import argparse
+import concurrent.futures as cf
 import json
-import multiprocessing as mp
 import os
 import sys
 import time
@@ -26,81 +34,54 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
-from oracle import field, lpt3, metrics, points, run  # noqa: E402
+from oracle import collapse, field, hessian, lpt3, metrics, run  # noqa: E402
 from paper_1305_1505_amd import workloads as W  # noqa: E402
 
-POINTS = {"c512_fp32": 64, "c768_fp32": 32}
+# name -> (workload, plan precision, F/R lattice stride, displacement lattice stride,
+#          displacements compared, radius indices (None = all))
+CASES = {
+    "c64_fp64": ("c64_fp64", "fp64", 1, 1, ("psi1", "psi2", "psi3"), None),
+    "c64_fp32": ("c64_fp64", "fp32", 1, 1, ("psi1", "psi2", "psi3"), None),
+    "c256_fp32": ("c256_fp32", "fp32", 2, 4, ("psi1", "psi2", "psi3"), None),
+    "c256_fp64": ("c256_fp32", "fp64", 4, 8, ("psi1", "psi2", "psi3"), None),
+    "c512_fp32": ("c512_fp32", "fp32", 4, 8, ("psi1", "psi2", "psi3"), None),
+    "c768_fp32": ("c768_fp32", "fp32", 6, 12, ("psi1",), (0, 11, 22, 33, 44)),
+}
 
 
-def _field(name):
-    cfg = W.CONFIGS[name]
-    return field.linear_field(cfg["seed"], cfg["n"], cfg["box"], W.SIGMA8, W.GAMMA, W.NS)
+def case_radii(case):
+    wl, _, _, _, _, sel = CASES[case]
+    radii = W.config_radii(W.CONFIGS[wl])
+    return radii if sel is None else np.array([radii[i] for i in sel])
 
 
-def job_radii(name, r0, r1):
-    """Running maximum over radii [r0, r1) with fresh state (oracle)."""
-    radii = W.config_radii(W.CONFIGS[name])
-    return ("radii", name, r0, run.collapse_times(_field(name), radii, r0, r1))
+def lattice(a, stride):
+    """The lattice points of a (..., N, N, N) array."""
+    return a[..., ::stride, ::stride, ::stride]
 
 
-def job_disp(name):
-    return ("disp", name, run.displacements(_field(name), W.CONFIGS[name]["box"]))
-
-
-def job_lpt3(name):
-    return ("lpt3", name, lpt3.lpt3_displacement(_field(name), W.CONFIGS[name]["box"]))
-
-
-def job_points(name, pts):
-    cfg = W.CONFIGS[name]
-    dk = _field(name)
-    fmax, ridx, _ = points.collapse_times_at_points(dk, pts, W.config_radii(cfg))
-    return ("points", name, pts, fmax, ridx, points.za_at_points(dk, pts, cfg["box"]))
-
-
-def sample_points(name):
-    n = W.CONFIGS[name]["n"]
-    rng = np.random.default_rng(W.CONFIGS[name]["seed"] + 7)
-    return [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(POINTS[name])]
-
-
-def merge(parts):
-    """Merge (r0, (fmax, ridx)) partial running maxima in radius order."""
-    parts = sorted(parts, key=lambda p: p[0])
-    fmax, ridx = parts[0][1]
-    for _, (f, r) in parts[1:]:
-        up = f > fmax
-        fmax = np.where(up, f, fmax)
-        ridx = np.where(up, r, ridx)
-    return fmax, ridx
-
-
-def gpu_outputs(lib, name, prec, pts=None, want_disp=True):
-    """GPU F, R_max (and psi1, psi2) on the host: full arrays, or only at `pts`."""
+# ------------------------------------------------------------------------------------------ GPU
+def gpu_case(lib, case):
     import torch
 
-    cfg = W.CONFIGS[name]
-    plan = lib.Plan(cfg["n"], cfg["box"], W.config_radii(cfg), sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=prec)
+    wl, precname, fs, ps, disp, _ = CASES[case]
+    cfg = W.CONFIGS[wl]
+    prec = lib.PIN_FP64 if precname == "fp64" else lib.PIN_FP32
+    plan = lib.Plan(cfg["n"], cfg["box"], case_radii(case), sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=prec)
     dk = plan.generate_field(cfg["seed"])
     F, R = plan.collapse_times(dk)
-    if pts is not None:
-        idx = torch.tensor(pts, device="cuda", dtype=torch.long)
-        at = lambda t: t[..., idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().astype(np.float64)
-        out = {"F": at(F), "R": at(R)}
-    else:
-        at = lambda t: t.cpu().numpy()   # native precision (float32 plans: float32)
-        out = {"F": at(F), "R": R.cpu().numpy()}
+    host = lambda t, s: lattice(t, s).contiguous().cpu().numpy()
+    out = {"F": host(F, fs), "R": host(R, fs)}
     del F, R
-    if want_disp:
-        p1, p2 = plan.displacements(dk, want_psi2=pts is None)
-        out["psi1"] = at(p1)
-        if p2 is not None:
-            out["psi2"] = at(p2)
-        del p1, p2
-        if pts is None:
-            p3 = plan.lpt3_displacement(dk)
-            out["psi3"] = at(p3)
-            del p3
+    p1, p2 = plan.displacements(dk, want_psi2="psi2" in disp)
+    out["psi1"] = host(p1, ps)
+    if p2 is not None:
+        out["psi2"] = host(p2, ps)
+    del p1, p2
+    if "psi3" in disp:
+        p3 = plan.lpt3_displacement(dk)
+        out["psi3"] = host(p3, ps)
+        del p3
     del dk
     plan.close()
     torch.cuda.synchronize()
@@ -108,129 +89,134 @@ def gpu_outputs(lib, name, prec, pts=None, want_disp=True):
     return out
 
 
-CASES = (("c64_fp64", "fp64"), ("c64_fp64", "fp32"), ("c256_fp32", "fp32"), ("c256_fp32", "fp64"),
-         ("c512_fp32", "fp32"), ("c768_fp32", "fp32"))
-SAMPLED = ("c512_fp32", "c768_fp32")
-
-
-def gpu_phase(path):
-    """Run every case on the GPU and save the outputs (host arrays) to `path` (.npz)."""
+def gpu_phase(path, cases):
     from paper_1305_1505_amd import binding as lib
 
     t0 = time.time()
     arrays = {}
-    for name, precname in CASES:
-        prec = lib.PIN_FP64 if precname == "fp64" else lib.PIN_FP32
-        if name == "c512_fp32":   # F at the sampled points, displacements on the full grid
-            g = gpu_outputs(lib, name, prec, pts=sample_points(name), want_disp=False)
-            g.update({k: v for k, v in gpu_outputs(lib, name, prec).items() if k.startswith("psi")})
-        elif name in SAMPLED:
-            g = gpu_outputs(lib, name, prec, pts=sample_points(name))
-        else:
-            g = gpu_outputs(lib, name, prec)
-        for k, v in g.items():
-            arrays[f"{name}|{precname}|{k}"] = v
-        print(f"[accuracy] GPU {name} {precname} done {time.time() - t0:.0f} s", flush=True)
+    for case in cases:
+        for k, v in gpu_case(lib, case).items():
+            arrays[f"{case}|{k}"] = v
+        print(f"[accuracy] GPU {case} done {time.time() - t0:.0f} s", flush=True)
     np.savez(path, **arrays)
+
+
+# --------------------------------------------------------------------------------------- oracle
+def oracle_F(dk, radii, stride, threads, mem_bytes):
+    """F_max and R_max index on the lattice: per radius the full-grid tensor (as many radii at
+    once, in threads, as mem_bytes allows; one component at a time above 512^3), read at the
+    lattice points, the collapse model there, and the running maximum in radius order."""
+    n = dk.shape[0]
+    per_radius = (4 if n > 512 else 9) * 8.0 * n ** 3
+    tthreads = max(1, min(threads, int(mem_bytes // per_radius)))
+
+    def tensor(radius):
+        if n > 512:
+            return [lattice(hessian.deformation_tensor(dk, radius, components=(ab,))[0], stride).ravel()
+                    for ab in hessian.COMPONENTS]
+        return [lattice(c, stride).ravel() for c in hessian.deformation_tensor(dk, radius)]
+
+    def model(t6):
+        m = t6[0].size
+        chunk = -(-m // (4 * threads))
+        with cf.ThreadPoolExecutor(threads) as ex:
+            parts = ex.map(lambda s: collapse.inverse_collapse_time([c[s:s + chunk] for c in t6]), range(0, m, chunk))
+            return np.concatenate(list(parts))
+
+    fmax = ridx = None
+    with cf.ThreadPoolExecutor(tthreads) as ex:
+        for r, t6 in enumerate(ex.map(tensor, radii)):
+            f = model(t6)
+            if fmax is None:
+                fmax = np.zeros_like(f)
+                ridx = np.full(f.shape, run.NEVER, dtype=np.uint8)
+            up = f > fmax
+            fmax = np.where(up, f, fmax)
+            ridx = np.where(up, np.uint8(r), ridx)
+    m = (n + stride - 1) // stride
+    return fmax.reshape(m, m, m), ridx.reshape(m, m, m)
+
+
+def oracle_case(case, threads, mem_bytes):
+    wl, _, fs, ps, disp, _ = CASES[case]
+    cfg = W.CONFIGS[wl]
+    dk = field.linear_field(cfg["seed"], cfg["n"], cfg["box"], W.SIGMA8, W.GAMMA, W.NS)
+    out = {}
+    out["F"], out["R"] = oracle_F(dk, case_radii(case), fs, threads, mem_bytes)
+    box = cfg["box"]
+    out["psi1"] = lattice(run.za_displacement(dk, box), ps)
+    if "psi2" in disp:
+        out["psi2"] = lattice(run.lpt2_displacement(dk, box), ps)
+    if "psi3" in disp:
+        out["psi3"] = lattice(lpt3.lpt3_displacement(dk, box), ps)
+    return out
+
+
+def compare(case, g, o):
+    wl, precname, fs, ps, disp, sel = CASES[case]
+    n = W.CONFIGS[wl]["n"]
+    row = {"case": case, "workload": wl, "plan": precname, "n": n,
+           "radii": len(case_radii(case)) if sel is None else f"{len(sel)} of {W.CONFIGS[wl]['n_radii']}",
+           "F_points": int(g["F"].size), "F_stride": fs,
+           "F_rel_rms": metrics.rel_rms(g["F"].astype(np.float64), o["F"]),
+           "F_rel_max": metrics.rel_max(g["F"].astype(np.float64), o["F"]),
+           "R_mismatch": float(np.mean(g["R"] != o["R"])), "R_mismatch_points": int(np.sum(g["R"] != o["R"])),
+           "psi_points": int(g["psi1"][0].size), "psi_stride": ps}
+    for k in disp:
+        row[f"{k}_rel_rms"] = metrics.rel_rms(g[k].astype(np.float64), o[k])
+        row[f"{k}_rel_max"] = metrics.rel_max(g[k].astype(np.float64), o[k])
+    return row
+
+
+def oracle_phase(gpu_path, out_json, md, threads, mem_bytes):
+    data = np.load(gpu_path)
+    gpu = {}
+    for key in data.files:
+        case, k = key.split("|")
+        gpu.setdefault(case, {})[k] = data[key]
+    rows = []
+    t0 = time.time()
+    for case in CASES:
+        if case not in gpu:
+            continue
+        row = compare(case, gpu[case], oracle_case(case, threads, mem_bytes))
+        rows.append(row)
+        print(f"[accuracy] {time.time() - t0:.0f} s " + json.dumps(row), flush=True)
+    with open(out_json, "w") as fh:
+        json.dump(rows, fh, indent=1)
+        fh.write("\n")
+    keys = ["case", "radii", "F_rel_rms", "F_rel_max", "R_mismatch", "F_points", "psi1_rel_rms", "psi1_rel_max",
+            "psi2_rel_rms", "psi2_rel_max", "psi3_rel_rms", "psi3_rel_max", "psi_points"]
+    fmt = lambda v: f"{v:.2e}" if isinstance(v, float) else str(v)
+    table = ["| " + " | ".join(keys) + " |", "|" + "---|" * len(keys)]
+    table += ["| " + " | ".join(fmt(r.get(k, "")) for k in keys) + " |" for r in rows]
+    print("\n".join(table))
+    if md:
+        with open(md, "a") as fh:
+            fh.write("\n".join(table) + "\n")
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workers", type=int, default=16)
-    ap.add_argument("--out", default=None)
-    ap.add_argument("--gpu-phase", default=None, help=argparse.SUPPRESS)
+    sub = ap.add_subparsers(dest="phase", required=True)
+    g = sub.add_parser("gpu")
+    g.add_argument("out")
+    g.add_argument("--cases", default=",".join(CASES))
+    o = sub.add_parser("oracle")
+    o.add_argument("gpu")
+    o.add_argument("out")
+    o.add_argument("--md", default=None)
+    o.add_argument("--threads", type=int, default=min(6, os.cpu_count() or 1))
+    o.add_argument("--mem-gb", type=float, default=30.0, help="host memory for full-grid tensors in flight")
     args = ap.parse_args()
-    if args.gpu_phase:
-        gpu_phase(args.gpu_phase)
-        return
-    t0 = time.time()
-    # the GPU work runs in a child process first; this process never initialises the GPU
-    import subprocess
-    import tempfile
-
-    tmp = os.path.join(tempfile.gettempdir(), f"pin_accuracy_{os.getpid()}.npz")
-    subprocess.run([sys.executable, "-u", os.path.abspath(__file__), "--gpu-phase", tmp], check=True)
-    data = np.load(tmp)
-    gpu = {}
-    for key in data.files:
-        name, precname, k = key.split("|")
-        gpu.setdefault((name, precname), {})[k] = data[key]
-    os.remove(tmp)
-
-    ctx = mp.get_context("spawn")
-    pool = ctx.Pool(args.workers)
-    pending = []
-    # quick jobs first, then one job per radius at 256^3 (about a minute each)
-    pending.append(pool.apply_async(job_radii, ("c64_fp64", 0, len(W.config_radii(W.CONFIGS["c64_fp64"])))))
-    for name in ("c64_fp64", "c256_fp32", "c512_fp32"):
-        pending.append(pool.apply_async(job_disp, (name,)))
-        pending.append(pool.apply_async(job_lpt3, (name,)))
-    for r0 in range(len(W.config_radii(W.CONFIGS["c256_fp32"]))):
-        pending.append(pool.apply_async(job_radii, ("c256_fp32", r0, r0 + 1)))
-    sampled = {name: sample_points(name) for name in SAMPLED}
-    for name, pts in sampled.items():
-        per = max(1, len(pts) // args.workers)
-        for i in range(0, len(pts), per):
-            pending.append(pool.apply_async(job_points, (name, pts[i:i + per])))
-    print(f"[accuracy] {len(pending)} oracle jobs queued", flush=True)
-
-    radii_parts, disp, pts_res, psi3 = {}, {}, {}, {}
-    for job in pending:
-        res = job.get()
-        if res[0] == "radii":
-            radii_parts.setdefault(res[1], []).append((res[2], res[3]))
-        elif res[0] == "disp":
-            disp[res[1]] = res[2]
-        elif res[0] == "lpt3":
-            psi3[res[1]] = res[2]
-        else:
-            pts_res.setdefault(res[1], []).append(res[2:])
-        print(f"[accuracy] oracle {res[0]} {res[1]} done {time.time() - t0:.0f} s", flush=True)
-    pool.close()
-
-    rows = []
-    for (name, precname), g in gpu.items():
-        label = f"{name} {precname} plan"
-        row = {"config": label}
-        if name in radii_parts:
-            fmax, ridx = merge(radii_parts[name])
-            rep = metrics.report(g["F"], fmax)
-            row.update(F_rel_rms=rep["rel_rms"], F_rel_max=rep["rel_max"], F_points="all",
-                       R_mismatch=metrics.mismatch_fraction(g["R"], ridx))
-        elif name in pts_res:
-            # oracle results in the order of `sampled[name]` (chunks were submitted in order)
-            pts = [p for chunk in pts_res[name] for p in chunk[0]]
-            assert pts == sampled[name]
-            fref = np.concatenate([c[1] for c in pts_res[name]])
-            rref = np.concatenate([c[2] for c in pts_res[name]])
-            row.update(F_rel_rms=metrics.rel_rms(g["F"], fref), F_rel_max=metrics.rel_max(g["F"], fref),
-                       F_points=len(pts), R_mismatch=float(np.mean(g["R"] != rref)))
-            if name not in disp:
-                zref = np.concatenate([c[3] for c in pts_res[name]])
-                z = g["psi1"].T
-                row.update(psi1_rel_rms=metrics.rel_rms(z, zref), psi1_rel_max=metrics.rel_max(z, zref),
-                           psi_points=len(pts))
-        if name in disp:
-            r1, r2 = disp[name]
-            row.update(psi1_rel_rms=metrics.rel_rms(g["psi1"], r1), psi1_rel_max=metrics.rel_max(g["psi1"], r1),
-                       psi2_rel_rms=metrics.rel_rms(g["psi2"], r2), psi2_rel_max=metrics.rel_max(g["psi2"], r2),
-                       psi_points="all")
-        if name in psi3 and "psi3" in g:
-            r3 = psi3[name]
-            row.update(psi3_rel_rms=metrics.rel_rms(g["psi3"], r3), psi3_rel_max=metrics.rel_max(g["psi3"], r3))
-        rows.append(row)
-        print("[accuracy] " + json.dumps(row), flush=True)
-
-    keys = ["config", "F_rel_rms", "F_rel_max", "R_mismatch", "F_points", "psi1_rel_rms", "psi1_rel_max",
-            "psi2_rel_rms", "psi2_rel_max", "psi3_rel_rms", "psi3_rel_max", "psi_points"]
-    fmt = lambda v: f"{v:.2e}" if isinstance(v, float) else str(v)
-    print("| " + " | ".join(keys) + " |")
-    print("|" + "---|" * len(keys))
-    for row in rows:
-        print("| " + " | ".join(fmt(row.get(k, "")) for k in keys) + " |")
-    if args.out:
-        with open(args.out, "w") as fh:
-            json.dump(rows, fh, indent=1)
+    if args.phase == "gpu":
+        cases = [c for c in args.cases.split(",") if c]
+        unknown = [c for c in cases if c not in CASES]
+        if unknown:
+            raise SystemExit(f"unknown cases {unknown}; known: {list(CASES)}")
+        gpu_phase(args.out, cases)
+    else:
+        oracle_phase(args.gpu, args.out, args.md, args.threads, args.mem_gb * 1e9)
 
 
 if __name__ == "__main__":

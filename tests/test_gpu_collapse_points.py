@@ -97,3 +97,89 @@ def test_empty_count_is_noop(lib):
     torch.cuda.synchronize()
     assert F.item() == 7.0
     plan.close()
+
+
+def near_cutoff_families(seed=21):
+    """Tensor families around the float64 epilogue's switches (float64 plans).
+
+    gap_sweep: lambda_1 - lambda_2 log-spaced from 1e-5 to 1e-1 of the spread lambda_1 - lambda_3,
+    across the switch from the closed form (polynomial in sqrt(1 + r) and Newton steps) to Jacobi
+    rotations at 1 + r = 1e-5, where the closed form's root is most sensitive to the rounding of
+    the characteristic polynomial's coefficients.
+
+    close_roots: the collapse cubic's two largest roots a relative 1e-5 to 1e-1 apart (real and
+    distinct), on both sides of its switch from the polynomial to acos/cos at cos(theta) =
+    -1 + 1e-8 (a relative gap of about 1e-4).  The largest root then moves by about eps/gap of
+    its size under a rounding of the coefficients, on both sides.  Built on the eigenvalues (l1, l2, l3): l3 is found by bisection where
+    the discriminant of P vanishes with the upper pair merging, then moved into the three-real
+    side and the root gap measured with numpy.roots.
+    """
+    rng = np.random.default_rng(seed)
+    fam = {}
+    n = 4000
+    l2 = rng.uniform(-2, 2, n)
+    l3 = l2 - rng.uniform(0.5, 2, n)
+    l1 = l2 + 10.0 ** rng.uniform(-5, -1, n) * (l2 - l3)
+    fam["gap_sweep"] = _rot(np.stack([l1, l2, l3], 1), rng)
+
+    def cubic(a, b, c):
+        mu2 = a * b + a * c + b * c
+        mu3 = a * b * c
+        d = a + b + c
+        return np.array([1.0, -a, -mu2 / 7.0, mu3 / 9.0 - 10.0 * d * mu2 / 189.0])
+
+    def disc(coef):
+        _, p2, p1, p0 = coef
+        a3 = p2 / 3.0
+        hq = 0.5 * (p0 - a3 * p1 + 2.0 * a3 ** 3)
+        p3 = (p1 - p2 * a3) / 3.0
+        return hq * hq + p3 ** 3
+
+    rows, gaps = [], []
+    while len(rows) < 1500:
+        a = rng.uniform(0.3, 2.0)
+        b = a * rng.uniform(-0.9, 0.9)
+        grid = np.linspace(-3.0 * a, b, 400)
+        dv = np.array([disc(cubic(a, b, c)) for c in grid])
+        for k in np.nonzero(np.sign(dv[:-1]) != np.sign(dv[1:]))[0]:
+            lo, hi = grid[k], grid[k + 1]
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                if np.sign(disc(cubic(a, b, mid))) == np.sign(disc(cubic(a, b, lo))):
+                    lo = mid
+                else:
+                    hi = mid
+            c0 = 0.5 * (lo + hi)
+            for frac in 10.0 ** rng.uniform(-11, -2, 4):
+                for c in (c0 * (1 + frac), c0 * (1 - frac)):
+                    if not b >= c:
+                        continue
+                    r = np.roots(cubic(a, b, c))
+                    if np.max(np.abs(r.imag)) > 0:
+                        continue
+                    r = np.sort(r.real)
+                    if r[2] <= 0 or r[1] < r[0] + 0.5 * (r[2] - r[0]):
+                        continue                     # the upper pair is the close one
+                    gap = (r[2] - r[1]) / r[2]
+                    if 1e-5 <= gap <= 1e-1:
+                        rows.append((a, b, c))
+                        gaps.append(gap)
+    lam = np.array(rows)
+    fam["close_roots"] = _rot(lam, rng)
+    fam["close_roots_gap"] = np.array(gaps)
+    return fam
+
+
+@pytest.mark.parametrize("name", ["gap_sweep", "close_roots"])
+def test_fp64_points_near_switches(lib, name):
+    """float64 plans at rounding accuracy on both sides of the epilogue's switches."""
+    fam = near_cutoff_families()
+    t6 = fam[name]
+    F = _run(lib, lib.PIN_FP64, t6)
+    ref = collapse.inverse_collapse_time(t6)
+    scale = np.max(np.abs(np.stack(t6)), axis=0)
+    err = np.abs(F - ref) / scale
+    # two roots a relative gap apart amplify a rounding of the cubic's coefficients ~1/gap-fold
+    bound = 1e-13 + (5e-15 / fam["close_roots_gap"] if name == "close_roots" else 0.0)
+    print(f"[points] {name}: fp64 worst {np.max(err):.3g}, worst / bound {np.max(err / bound):.3g}", flush=True)
+    assert np.all(err <= bound), name

@@ -9,7 +9,9 @@ the field it produced -- checked against the FP64 oracle:
   F = 0, radius-range splitting bit-identical to one call, psi2 a gradient field.
 
 Sample points are fixed corners and Nyquist-adjacent indices plus seeded random ones; nothing
-the oracle sees comes from the GPU.
+the oracle sees comes from the GPU.  For 384^3, 512^3 and 768^3 the oracle's F_max, R_max and
+per-radius F at 1024 points come from tests/golden/fullsize_points_<workload>.npz, written by
+tests/golden/make_fullsize_points.py (oracle only: full-grid tensors read at the points).
 
 Tolerances (float32 FFTs, float64-computed twiddles): intermediate fields carry an absolute
 error of a few eps32 * log2(N) of their RMS; a collapse time F ~ lambda_1 inherits it.  Per
@@ -19,11 +21,12 @@ at the GPU's radius is within that tolerance of its maximum.
 """
 
 import functools
+import os
 
 import numpy as np
 import pytest
 
-from oracle import field, hessian, points
+from oracle import field, hessian, metrics, points
 from paper_1305_1505_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -248,3 +251,64 @@ def test_largest_grid_1024(lib):
     # move a large fraction
     assert rms <= 1e-5 and off <= 1e-6 and mism <= 1e-4
     p1024.close()
+
+
+GOLDEN = ["s384_fp32", "c512_fp32", "c768_fp32"]
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", GOLDEN)
+def test_fullsize_collapse_at_golden_points(lib, name):
+    """F_max and R_max at 1024 grid points against the oracle's stored values (same workload,
+    same seed, every radius), in the launch configuration bench.py times."""
+    cfg = W.CONFIGS[name]
+    radii = W.config_radii(cfg)
+    g = np.load(os.path.join(GOLDEN_DIR, f"fullsize_points_{name}.npz"))
+    assert int(g["n"]) == cfg["n"] and float(g["box"]) == cfg["box"] and int(g["seed"]) == cfg["seed"]
+    assert np.allclose(g["radii"], radii, rtol=1e-15, atol=0)
+    pts = [tuple(int(v) for v in p) for p in g["points"]]
+    fmax, ridx, fr = g["fmax"], g["ridx"].astype(np.int64), g["f_per_radius"].astype(np.float64)
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    F, R = plan.collapse_times(dk)
+    f_gpu = _at(F, pts)
+    r_gpu = _at(R, pts).astype(np.int64)
+    plan.close()
+    tol = 1e-4 * float(g["sigma_rmin"])
+    d = np.abs(f_gpu - fmax)
+    moved = np.nonzero(r_gpu != ridx)[0]
+    print(f"[fullsize] {name}: {len(pts)} points, F rel RMS {metrics.rel_rms(f_gpu, fmax):.3g}, "
+          f"rel max {metrics.rel_max(f_gpu, fmax):.3g}, max |dF| / tol {np.max(d) / tol:.3g}, "
+          f"R_max differs at {len(moved)}", flush=True)
+    assert metrics.rel_rms(f_gpu, fmax) <= 1e-5
+    assert np.all(d <= tol), f"worst point {pts[int(np.argmax(d))]}"
+    # a different R_max only where the oracle's F at the GPU's radius ties its maximum within tol
+    for p in moved:
+        assert r_gpu[p] != 255 and abs(fr[p, r_gpu[p]] - fmax[p]) <= tol + 1e-7 * abs(fmax[p]), f"point {pts[p]}"
+
+
+@pytest.mark.timeout(600)
+def test_serving_size_192_tensor_full_grid(lib):
+    """192^3 (radix-3 factorisation of the serving trace's sizes), float32: all six tensor
+    components on the whole grid at the largest and smallest radius against the oracle."""
+    import torch
+
+    name = "s192_fp32"
+    cfg = W.CONFIGS[name]
+    radii = W.config_radii(cfg)
+    ref_dk = field.linear_field(cfg["seed"], cfg["n"], cfg["box"], W.SIGMA8, W.GAMMA, W.NS)
+    plan = _plan(lib, name)
+    dk = plan.generate_field(cfg["seed"])
+    for r in (0, len(radii) - 1):
+        t6 = plan.deformation_tensor(dk, r)
+        torch.cuda.synchronize()
+        got = t6.cpu().numpy().astype(np.float64)
+        del t6
+        ref = hessian.deformation_tensor(ref_dk, radii[r])
+        for c in range(6):
+            rms, mx = metrics.rel_rms(got[c], ref[c]), metrics.rel_max(got[c], ref[c])
+            assert rms <= 2e-6 and mx <= 1e-5, f"radius {r} component {c}: {rms:.3g} {mx:.3g}"
+        print(f"[fullsize] 192^3 radius {r}: worst component rel RMS "
+              f"{max(metrics.rel_rms(got[c], ref[c]) for c in range(6)):.3g}", flush=True)
+    plan.close()

@@ -56,6 +56,9 @@ REQS = [
     dict(seed=14, n=48, box=96.0, radii=W.radii_cells(5, 10.0, 0.75), disp=1),
     dict(seed=11, n=64, box=128.0, radii=W.radii_cells(12, 20.0, 0.75), disp=1),   # = REQS[0]
     dict(seed=16, n=64, box=100.0, radii=W.radii_cells(7, 20.0, 1.0), disp=0),
+    # serving-trace sizes with radix-3 factorisations
+    dict(seed=17, n=192, box=384.0, radii=W.radii_cells(10, 60.0, 0.75), disp=1),
+    dict(seed=18, n=384, box=768.0, radii=W.radii_cells(6, 60.0, 0.75), disp=0),
 ]
 
 
