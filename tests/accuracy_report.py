@@ -6,7 +6,7 @@ Two phases, so that the oracle's hours of host work need no GPU and the GPU's ou
 bounded transfer:
 
     python tests/accuracy_report.py gpu <out.npz> [--cases A,B,...]      # on the GPU
-    python tests/accuracy_report.py oracle <gpu.npz> <out.json> [--md out.md] [--threads 6]
+    python tests/accuracy_report.py oracle <gpu.npz> <out.json> [--md out.md] [--threads 6] [--cache DIR]
 
 The GPU phase runs each case through the C ABI in the launch configuration bench.py uses (one
 plan, pin_generate_field, pin_collapse_times, pin_displacements, pin_lpt3_displacement) and keeps
@@ -168,7 +168,22 @@ def compare(case, g, o):
     return row
 
 
-def oracle_phase(gpu_path, out_json, md, threads, mem_bytes):
+def cached_oracle_case(case, threads, mem_bytes, cache):
+    """oracle_case, kept in `cache` (a directory; None: no cache): the oracle's lattice values do
+    not depend on the GPU code, so a later comparison reuses them."""
+    if cache is None:
+        return oracle_case(case, threads, mem_bytes)
+    os.makedirs(cache, exist_ok=True)
+    path = os.path.join(cache, f"oracle_{case}.npz")
+    if os.path.exists(path):
+        with np.load(path) as d:
+            return {k: d[k] for k in d.files}
+    out = oracle_case(case, threads, mem_bytes)
+    np.savez(path, **out)
+    return out
+
+
+def oracle_phase(gpu_path, out_json, md, threads, mem_bytes, cache=None):
     data = np.load(gpu_path)
     gpu = {}
     for key in data.files:
@@ -179,7 +194,7 @@ def oracle_phase(gpu_path, out_json, md, threads, mem_bytes):
     for case in CASES:
         if case not in gpu:
             continue
-        row = compare(case, gpu[case], oracle_case(case, threads, mem_bytes))
+        row = compare(case, gpu[case], cached_oracle_case(case, threads, mem_bytes, cache))
         rows.append(row)
         print(f"[accuracy] {time.time() - t0:.0f} s " + json.dumps(row), flush=True)
     with open(out_json, "w") as fh:
@@ -208,6 +223,7 @@ def main():
     o.add_argument("--md", default=None)
     o.add_argument("--threads", type=int, default=min(6, os.cpu_count() or 1))
     o.add_argument("--mem-gb", type=float, default=30.0, help="host memory for full-grid tensors in flight")
+    o.add_argument("--cache", default=None, help="directory keeping the oracle's lattice values per case")
     args = ap.parse_args()
     if args.phase == "gpu":
         cases = [c for c in args.cases.split(",") if c]
@@ -216,7 +232,7 @@ def main():
             raise SystemExit(f"unknown cases {unknown}; known: {list(CASES)}")
         gpu_phase(args.out, cases)
     else:
-        oracle_phase(args.gpu, args.out, args.md, args.threads, args.mem_gb * 1e9)
+        oracle_phase(args.gpu, args.out, args.md, args.threads, args.mem_gb * 1e9, args.cache)
 
 
 if __name__ == "__main__":
