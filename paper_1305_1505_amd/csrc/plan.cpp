@@ -1,7 +1,10 @@
 // Plan creation, tables and the launch sequences of the path.
 #include "plan.hpp"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <cmath>
+#include <cstdio>
 #include <new>
 
 #include "host_math.hpp"
@@ -10,6 +13,20 @@ namespace pin {
 
 namespace {
 thread_local std::string g_last_error;
+
+// A host-side roctx range around the enqueue of one step of the path: rocprofv3 --marker-trace
+// shows it beside the kernels it launched.
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  Range(const char* what, int n, int r) {
+    char name[64];
+    std::snprintf(name, sizeof name, "%s N=%d r=%d", what, n, r);
+    roctxRangePushA(name);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // Copy a float64 host table to the device in the plan's precision; waits for the copy (the host
 // staging buffer is local).
@@ -192,6 +209,7 @@ void plan_set_radii(pin_plan p, const double* radii, int n_radii, hipStream_t s)
 }
 
 void plan_generate_field(pin_plan p, uint64_t seed, void* dk, hipStream_t s) {
+  Range range("pin field");
   const double* amp = amp_table(p);
   p->launch(KC_GRF, s, [&] { p->ops->grf(dk, seed, amp, s); });
 }
@@ -203,6 +221,7 @@ void plan_reset(pin_plan p, void* F, uint8_t* ridx, hipStream_t s) {
 void plan_run_radii(pin_plan p, const void* dk, void* F, uint8_t* ridx, int r0, int r1, hipStream_t s) {
   prep_hessian_input(p, dk, s);
   for (int r = r0; r < r1; ++r) {
+    Range range("pin radius", p->n, r);
     const void* w = p->window_row(r);
     p->launch(KC_XPASS_HESS, s, [&] { p->ops->xpass(0, p->G, p->X, w, p->tw, 1.0, s); });
     p->launch(KC_YPASS_HESS, s, [&] { p->ops->ypass(0, p->X, p->Y, p->tw, s); });
@@ -243,6 +262,7 @@ void plan_deformation_tensor(pin_plan p, const void* dk, int r, void* T6, hipStr
 }
 
 void plan_displacements(pin_plan p, const void* dk, void* psi1, void* psi2, hipStream_t s) {
+  Range range("pin displacements");
   const double n3 = (double)p->n * p->n * p->n;
   const double lfac = p->box / (2.0 * 3.14159265358979323846);
   if (psi1) {
@@ -273,6 +293,7 @@ size_t lpt3_workspace_bytes(int n, bool fp64) {
 }
 
 void plan_lpt3_displacement(pin_plan p, const void* dk, void* psi3, hipStream_t s) {
+  Range range("pin 3lpt displacement");
   if (p->L == nullptr) p->L = device_alloc(lpt3_workspace_bytes(p->n, p->fp64), "workspace L");
   const double n3 = (double)p->n * p->n * p->n;
   const double lfac = p->box / (2.0 * 3.14159265358979323846);

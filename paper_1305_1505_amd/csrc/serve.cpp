@@ -1,7 +1,9 @@
 // HIP executor of the serving scheduler: slots are plans plus per-request buffers and a stream;
 // a request is the field kernel followed by one captured hipGraph of the rest of its path.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
+#include <cstdio>
 #include <map>
 #include <tuple>
 
@@ -25,6 +27,8 @@ struct HipSlot {
   // most kMaxGraphs, the least recently used dropped first
   std::map<std::tuple<int, double, int>, std::pair<hipGraphExec_t, uint64_t>> graphs;
   uint64_t launches = 0;
+  // roctx range from the request's launch to the poll that sees it done (0: none open)
+  roctx_range_id_t range = 0;
 };
 
 class HipExec {
@@ -92,6 +96,10 @@ class HipExec {
 
   void launch(Slot* s, uint64_t seed, double box, const std::vector<double>& radii, int want_disp) {
     hip_check(hipSetDevice(cfg_.device), "hipSetDevice");
+    char name[96];
+    std::snprintf(name, sizeof name, "pin request N=%d radii=%d seed=%llu", s->n, (int)radii.size(),
+                  (unsigned long long)seed);
+    s->range = roctxRangeStartA(name);
     pin_plan p = s->plan;
     plan_set_radii(p, radii.data(), (int)radii.size(), s->stream);
     p->box = box;
@@ -116,8 +124,12 @@ class HipExec {
 
   int poll(Slot* s, std::string& err) {
     const hipError_t e = hipEventQuery(s->done);
-    if (e == hipSuccess) return 1;
     if (e == hipErrorNotReady) return 0;
+    if (s->range != 0) {
+      roctxRangeStop(s->range);
+      s->range = 0;
+    }
+    if (e == hipSuccess) return 1;
     (void)hipGetLastError();
     err = std::string("device error: ") + hipGetErrorString(e);
     return -1;
