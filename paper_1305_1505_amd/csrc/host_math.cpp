@@ -288,14 +288,18 @@ double eds_sphere_root() {
 
 double eds_delta_c() { return 0.15 * std::pow(12.0 * kPi, 2.0 / 3.0); }
 
-std::vector<double> twiddles(int n) {
-  std::vector<double> t(2 * (size_t)n);
+void twiddles_into(int n, double* out) {
   for (int m = 0; m < n; ++m) {
     // angle in extended precision, then rounded once to float64
     const long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
-    t[2 * m] = (double)std::cos(ang);
-    t[2 * m + 1] = (double)std::sin(ang);
+    out[2 * m] = (double)std::cos(ang);
+    out[2 * m + 1] = (double)std::sin(ang);
   }
+}
+
+std::vector<double> twiddles(int n) {
+  std::vector<double> t(2 * (size_t)n);
+  twiddles_into(n, t.data());
   return t;
 }
 

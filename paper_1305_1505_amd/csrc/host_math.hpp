@@ -50,6 +50,8 @@ double eds_sphere_root();
 double eds_delta_c();
 // exp(2 pi i m/N), m < N, interleaved (re, im)
 std::vector<double> twiddles(int n);
+// The same table written to out[2n] (no allocation).
+void twiddles_into(int n, double* out);
 // exp(-(2 pi f(i) R/N)^2 / 2) for i < N, f(i) the integer frequency of index i
 std::vector<double> gaussian_window_table(int n, double radius_cells);
 

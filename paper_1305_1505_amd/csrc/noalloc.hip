@@ -78,8 +78,7 @@ __global__ void k_noalloc_windows(R* w, WindowArgs a) {
 template <typename R>
 void write_tables(void* tw, void* wtab, const pin_plan_desc* d, hipStream_t s) {
   TwiddleArgs ta{};
-  const std::vector<double> t = twiddles(d->n);
-  for (size_t i = 0; i < t.size(); ++i) ta.v[i] = t[i];
+  twiddles_into(d->n, ta.v);   // n <= kMaxN, checked by the caller
   ta.n = d->n;
   WindowArgs wa{};
   for (int r = 0; r < d->n_radii; ++r) wa.radius[r] = d->radii_cells[r];
