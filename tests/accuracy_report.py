@@ -5,13 +5,18 @@ collapse radius R_max differs (float32 and float64 plans).
 Two phases, so that the oracle's hours of host work need no GPU and the GPU's output fits a
 bounded transfer:
 
-    python tests/accuracy_report.py gpu <out.npz> [--cases A,B,...]      # on the GPU
-    python tests/accuracy_report.py oracle <gpu.npz> <out.json> [--md out.md] [--threads 6] [--cache DIR]
+    python tests/accuracy_report.py gpu <out.npz> [--cases A,B,...] [--part P]   # on the GPU
+    python tests/accuracy_report.py oracle <gpu.npz> [<gpu.npz> ...] --out <out.json> [--md out.md]
+                                   [--threads 6] [--cache DIR]
+    python tests/accuracy_report.py prepare --cases A,B --cache DIR    # oracle side ahead of time
 
 The GPU phase runs each case through the C ABI in the launch configuration bench.py uses (one
 plan, pin_generate_field, pin_collapse_times, pin_displacements, pin_lpt3_displacement) and keeps
 the outputs on a lattice of grid points: every `stride`-th point along each axis (stride 1 = the
-whole grid), one lattice for F_max and R_max and a coarser one for the displacements.  The oracle
+whole grid), one lattice for F_max and R_max and a coarser one for the displacements.  A case
+whose F_max/R_max lattice is too large for one transfer is cut into parts of `slab` x-planes:
+`--part P` keeps planes [P*slab, (P+1)*slab) (part 0 also keeps the displacements), saved
+compressed, and the oracle phase joins the parts of all the files it is given.  The oracle
 phase computes the same quantities on the whole grid from the oracle (field, deformation tensors
 per radius, collapse model, running maximum, displacements) and reads them at the same lattice
 points; nothing in it comes from the GPU.  The 768^3 case runs five of its radii (the first, the
@@ -23,7 +28,9 @@ rel_max = max|x - x_o| / max|x_o|, R mismatch = fraction of points whose R_max i
 """
 
 import argparse
+import collections
 import concurrent.futures as cf
+import itertools
 import json
 import os
 import sys
@@ -38,19 +45,28 @@ from oracle import collapse, field, hessian, lpt3, metrics, run  # noqa: E402
 from paper_1305_1505_amd import workloads as W  # noqa: E402
 
 # name -> (workload, plan precision, F/R lattice stride, displacement lattice stride,
-#          displacements compared, radius indices (None = all))
+#          displacements compared, radius indices (None = all), x-planes per part (None = one part))
 CASES = {
-    "c64_fp64": ("c64_fp64", "fp64", 1, 1, ("psi1", "psi2", "psi3"), None),
-    "c64_fp32": ("c64_fp64", "fp32", 1, 1, ("psi1", "psi2", "psi3"), None),
-    "c256_fp32": ("c256_fp32", "fp32", 2, 4, ("psi1", "psi2", "psi3"), None),
-    "c256_fp64": ("c256_fp32", "fp64", 4, 8, ("psi1", "psi2", "psi3"), None),
-    "c512_fp32": ("c512_fp32", "fp32", 4, 8, ("psi1", "psi2", "psi3"), None),
-    "c768_fp32": ("c768_fp32", "fp32", 6, 12, ("psi1",), (0, 11, 22, 33, 44)),
+    "c64_fp64": ("c64_fp64", "fp64", 1, 1, ("psi1", "psi2", "psi3"), None, None),
+    "c64_fp32": ("c64_fp64", "fp32", 1, 1, ("psi1", "psi2", "psi3"), None, None),
+    "c256_fp32": ("c256_fp32", "fp32", 2, 4, ("psi1", "psi2", "psi3"), None, None),
+    "c256_fp64": ("c256_fp32", "fp64", 4, 8, ("psi1", "psi2", "psi3"), None, None),
+    "c512_fp32": ("c512_fp32", "fp32", 1, 8, ("psi1", "psi2", "psi3"), None, 52),
+    "c768_fp32": ("c768_fp32", "fp32", 6, 12, ("psi1",), (0, 11, 22, 33, 44), None),
 }
 
 
+def case_parts(case):
+    """Number of GPU parts of a case (lattice x-planes split by `slab`)."""
+    wl, _, fs, _, _, _, slab = CASES[case]
+    if slab is None:
+        return 1
+    m = (W.CONFIGS[wl]["n"] + fs - 1) // fs
+    return (m + slab - 1) // slab
+
+
 def case_radii(case):
-    wl, _, _, _, _, sel = CASES[case]
+    wl, _, _, _, _, sel, _ = CASES[case]
     radii = W.config_radii(W.CONFIGS[wl])
     return radii if sel is None else np.array([radii[i] for i in sel])
 
@@ -61,18 +77,28 @@ def lattice(a, stride):
 
 
 # ------------------------------------------------------------------------------------------ GPU
-def gpu_case(lib, case):
+def gpu_case(lib, case, part=0):
     import torch
 
-    wl, precname, fs, ps, disp, _ = CASES[case]
+    wl, precname, fs, ps, disp, _, slab = CASES[case]
     cfg = W.CONFIGS[wl]
     prec = lib.PIN_FP64 if precname == "fp64" else lib.PIN_FP32
     plan = lib.Plan(cfg["n"], cfg["box"], case_radii(case), sigma8=W.SIGMA8, gamma=W.GAMMA, ns=W.NS, prec=prec)
     dk = plan.generate_field(cfg["seed"])
     F, R = plan.collapse_times(dk)
     host = lambda t, s: lattice(t, s).contiguous().cpu().numpy()
-    out = {"F": host(F, fs), "R": host(R, fs)}
+    if slab is None:
+        out = {"F": host(F, fs), "R": host(R, fs)}
+    else:
+        lo = part * slab
+        out = {f"F@{lo}": host(lattice(F, fs)[lo:lo + slab], 1), f"R@{lo}": host(lattice(R, fs)[lo:lo + slab], 1)}
     del F, R
+    if part > 0:
+        del dk
+        plan.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out
     p1, p2 = plan.displacements(dk, want_psi2="psi2" in disp)
     out["psi1"] = host(p1, ps)
     if p2 is not None:
@@ -89,26 +115,73 @@ def gpu_case(lib, case):
     return out
 
 
-def gpu_phase(path, cases):
+def gpu_phase(path, cases, part=None):
     from paper_1305_1505_amd import binding as lib
 
     t0 = time.time()
     arrays = {}
     for case in cases:
-        for k, v in gpu_case(lib, case).items():
+        if part is not None and not 0 <= part < case_parts(case):
+            raise SystemExit(f"{case} has parts 0..{case_parts(case) - 1}")
+        for k, v in gpu_case(lib, case, part or 0).items():
             arrays[f"{case}|{k}"] = v
-        print(f"[accuracy] GPU {case} done {time.time() - t0:.0f} s", flush=True)
-    np.savez(path, **arrays)
+        print(f"[accuracy] GPU {case} part {part or 0} done {time.time() - t0:.0f} s", flush=True)
+    (np.savez if part is None else np.savez_compressed)(path, **arrays)
+
+
+def load_gpu(paths):
+    """The GPU outputs of several files, per case; the parts F@lo / R@lo of a split case are
+    joined along x and must cover its whole lattice."""
+    gpu = {}
+    for path in paths:
+        with np.load(path) as data:
+            for key in data.files:
+                case, k = key.split("|")
+                gpu.setdefault(case, {})[k] = data[key]
+    for case, g in gpu.items():
+        for q in ("F", "R"):
+            parts = sorted((int(k.split("@")[1]), k) for k in g if k.startswith(q + "@"))
+            if not parts:
+                continue
+            lo = 0
+            for start, k in parts:
+                if start != lo:
+                    raise SystemExit(f"{case}: {q} parts do not cover planes from {lo}")
+                lo += g[k].shape[0]
+            g[q] = np.concatenate([g.pop(k) for _, k in parts])
+            want = lattice(np.empty((W.CONFIGS[CASES[case][0]]["n"],) * 3, np.uint8), CASES[case][2]).shape
+            if g[q].shape != want:
+                raise SystemExit(f"{case}: {q} parts cover {g[q].shape}, lattice is {want}")
+    return gpu
 
 
 # --------------------------------------------------------------------------------------- oracle
+def bounded_map(ex, fn, items, ahead):
+    """fn over items in order, at most `ahead` results computed ahead of the one being used
+    (0: one at a time, nothing ahead), so that large results do not pile up in memory."""
+    if ahead <= 0:
+        for x in items:
+            yield fn(x)
+        return
+    items = iter(items)
+    futs = collections.deque(ex.submit(fn, x) for x in itertools.islice(items, ahead))
+    while futs:
+        res = futs.popleft().result()
+        nxt = next(items, None)
+        if nxt is not None:
+            futs.append(ex.submit(fn, nxt))
+        yield res
+        del res
+
+
 def oracle_F(dk, radii, stride, threads, mem_bytes):
-    """F_max and R_max index on the lattice: per radius the full-grid tensor (as many radii at
-    once, in threads, as mem_bytes allows; one component at a time above 512^3), read at the
-    lattice points, the collapse model there, and the running maximum in radius order."""
+    """F_max and R_max index on the lattice: per radius the full-grid tensor (computed ahead in
+    threads for as many radii as mem_bytes allows beside the one in use; one component at a time
+    above 512^3), read at the lattice points, the collapse model there, and the running maximum
+    in radius order."""
     n = dk.shape[0]
     per_radius = (4 if n > 512 else 9) * 8.0 * n ** 3
-    tthreads = max(1, min(threads, int(mem_bytes // per_radius)))
+    ahead = max(0, min(threads, int(mem_bytes // per_radius) - 1))
 
     def tensor(radius):
         if n > 512:
@@ -118,27 +191,31 @@ def oracle_F(dk, radii, stride, threads, mem_bytes):
 
     def model(t6):
         m = t6[0].size
-        chunk = -(-m // (4 * threads))
+        chunk = min(-(-m // (4 * threads)), 1 << 20)
         with cf.ThreadPoolExecutor(threads) as ex:
             parts = ex.map(lambda s: collapse.inverse_collapse_time([c[s:s + chunk] for c in t6]), range(0, m, chunk))
             return np.concatenate(list(parts))
 
     fmax = ridx = None
-    with cf.ThreadPoolExecutor(tthreads) as ex:
-        for r, t6 in enumerate(ex.map(tensor, radii)):
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(max(1, ahead)) as ex:
+        for r, t6 in enumerate(bounded_map(ex, tensor, radii, ahead)):
             f = model(t6)
+            del t6
             if fmax is None:
                 fmax = np.zeros_like(f)
                 ridx = np.full(f.shape, run.NEVER, dtype=np.uint8)
             up = f > fmax
             fmax = np.where(up, f, fmax)
             ridx = np.where(up, np.uint8(r), ridx)
+            del f, up
+            print(f"[accuracy] oracle N={n} radius {r + 1}/{len(radii)} {time.time() - t0:.0f} s", flush=True)
     m = (n + stride - 1) // stride
     return fmax.reshape(m, m, m), ridx.reshape(m, m, m)
 
 
 def oracle_case(case, threads, mem_bytes):
-    wl, _, fs, ps, disp, _ = CASES[case]
+    wl, _, fs, ps, disp, _, _ = CASES[case]
     cfg = W.CONFIGS[wl]
     dk = field.linear_field(cfg["seed"], cfg["n"], cfg["box"], W.SIGMA8, W.GAMMA, W.NS)
     out = {}
@@ -153,7 +230,7 @@ def oracle_case(case, threads, mem_bytes):
 
 
 def compare(case, g, o):
-    wl, precname, fs, ps, disp, sel = CASES[case]
+    wl, precname, fs, ps, disp, sel, _ = CASES[case]
     n = W.CONFIGS[wl]["n"]
     row = {"case": case, "workload": wl, "plan": precname, "n": n,
            "radii": len(case_radii(case)) if sel is None else f"{len(sel)} of {W.CONFIGS[wl]['n_radii']}",
@@ -183,12 +260,8 @@ def cached_oracle_case(case, threads, mem_bytes, cache):
     return out
 
 
-def oracle_phase(gpu_path, out_json, md, threads, mem_bytes, cache=None):
-    data = np.load(gpu_path)
-    gpu = {}
-    for key in data.files:
-        case, k = key.split("|")
-        gpu.setdefault(case, {})[k] = data[key]
+def oracle_phase(gpu_paths, out_json, md, threads, mem_bytes, cache=None):
+    gpu = load_gpu(gpu_paths)
     rows = []
     t0 = time.time()
     for case in CASES:
@@ -217,20 +290,32 @@ def main():
     g = sub.add_parser("gpu")
     g.add_argument("out")
     g.add_argument("--cases", default=",".join(CASES))
+    g.add_argument("--part", type=int, default=None, help="part of a case split into x-plane slabs")
     o = sub.add_parser("oracle")
-    o.add_argument("gpu")
-    o.add_argument("out")
+    o.add_argument("gpu", nargs="+")
+    o.add_argument("--out", required=True)
     o.add_argument("--md", default=None)
     o.add_argument("--threads", type=int, default=min(6, os.cpu_count() or 1))
     o.add_argument("--mem-gb", type=float, default=30.0, help="host memory for full-grid tensors in flight")
     o.add_argument("--cache", default=None, help="directory keeping the oracle's lattice values per case")
+    c = sub.add_parser("prepare", help="fill the oracle cache for some cases, before any GPU output exists")
+    c.add_argument("--cases", required=True)
+    c.add_argument("--cache", required=True)
+    c.add_argument("--threads", type=int, default=min(6, os.cpu_count() or 1))
+    c.add_argument("--mem-gb", type=float, default=30.0)
     args = ap.parse_args()
+    if args.phase == "prepare":
+        for case in (c for c in args.cases.split(",") if c):
+            t0 = time.time()
+            cached_oracle_case(case, args.threads, args.mem_gb * 1e9, args.cache)
+            print(f"[accuracy] oracle {case} cached {time.time() - t0:.0f} s", flush=True)
+        return
     if args.phase == "gpu":
         cases = [c for c in args.cases.split(",") if c]
         unknown = [c for c in cases if c not in CASES]
         if unknown:
             raise SystemExit(f"unknown cases {unknown}; known: {list(CASES)}")
-        gpu_phase(args.out, cases)
+        gpu_phase(args.out, cases, args.part)
     else:
         oracle_phase(args.gpu, args.out, args.md, args.threads, args.mem_gb * 1e9, args.cache)
 

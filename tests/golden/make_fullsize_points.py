@@ -1,7 +1,7 @@
 """Write the FP64 oracle's collapse times at sampled grid points of the large workloads, for
 tests/test_gpu_fullsize.py: tests/golden/fullsize_points_<workload>.npz.
 
-    python tests/golden/make_fullsize_points.py [workload ...] [--threads 3]
+    python tests/golden/make_fullsize_points.py [workload ...] [--threads 3] [--resume DIR]
 
 Default workloads: s384_fp32, c512_fp32, c768_fp32 (384^3, 512^3 and 768^3 grids).  For each: the
 seeded linear field (oracle.field), then per radius the deformation tensor on the full grid
@@ -10,6 +10,9 @@ threads), read at the points; the collapse model (oracle.collapse) at the points
 radius and the running maximum (radii largest first, strict '>' to update, 0 and index 255
 before any), as oracle.run does on the full grid.  Also stored: the rms of one tensor component
 at the smallest radius (Parseval on the oracle field), the scale of the tests' tolerances.
+
+With --resume, each radius's tensor at the points is also kept in DIR and read back on a later
+run, so that an interrupted run goes on where it stopped.
 
 Points: the three fixed corner / Nyquist-adjacent indices of the tests, then seeded random ones
 (numpy default_rng(seed * 10 + 3)), 1024 in all.  Nothing here reads GPU output.
@@ -53,7 +56,7 @@ def component_rms(dk, radius):
     return np.sqrt(tot) / float(n) ** 3 / np.sqrt(3.0)
 
 
-def make(name, threads):
+def make(name, threads, resume=None):
     cfg = W.CONFIGS[name]
     n = cfg["n"]
     radii = W.config_radii(cfg)
@@ -63,17 +66,25 @@ def make(name, threads):
     print(f"[golden] {name}: field {time.time() - t0:.0f} s", flush=True)
     ix, iy, iz = pts[:, 0], pts[:, 1], pts[:, 2]
 
-    def tensor_at(radius):
+    def tensor_at(r):
+        keep = None if resume is None else os.path.join(resume, f"{name}_r{r:03d}.npy")
+        if keep is not None and os.path.exists(keep):
+            return np.load(keep)
         out = np.empty((len(pts), 6))
         for c, ab in enumerate(hessian.COMPONENTS):
-            comp = hessian.deformation_tensor(dk, radius, components=(ab,))[0]
+            comp = hessian.deformation_tensor(dk, radii[r], components=(ab,))[0]
             out[:, c] = comp[ix, iy, iz]
             del comp
+        if keep is not None:
+            np.save(keep + ".tmp.npy", out)
+            os.replace(keep + ".tmp.npy", keep)
         return out
 
+    if resume is not None:
+        os.makedirs(resume, exist_ok=True)
     with cf.ThreadPoolExecutor(threads) as ex:
         tens = []
-        for r, t in enumerate(ex.map(tensor_at, radii)):
+        for r, t in enumerate(ex.map(tensor_at, range(len(radii)))):
             tens.append(t)
             print(f"[golden] {name}: radius {r + 1}/{len(radii)} {time.time() - t0:.0f} s", flush=True)
     tens = np.stack(tens, axis=1)                                   # (P, n_radii, 6)
@@ -94,9 +105,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workloads", nargs="*", default=["s384_fp32", "c512_fp32", "c768_fp32"])
     ap.add_argument("--threads", type=int, default=3)
+    ap.add_argument("--resume", default=None, help="directory keeping each radius's tensor at the points")
     args = ap.parse_args()
     for name in args.workloads:
-        make(name, args.threads)
+        make(name, args.threads, args.resume)
 
 
 if __name__ == "__main__":
