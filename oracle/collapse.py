@@ -33,6 +33,12 @@ R1 -- quasi-spherical correction.
 Arithmetic: float64 throughout.  lambda_1 comes from LAPACK (numpy.linalg.eigvalsh); the cubic's
 largest real root is bracketed with the critical points of P (closed form) and found by
 bisection.
+
+Pins (tests/test_oracle_collapse.py): delta_c and the sphere series against the exact EdS
+collapse, sphere and plane limits, homogeneity, the root finder against numpy.roots, and each
+coefficient of P against the Zel'dovich, 2LPT and 3LPT oracles (which the equations of motion
+pin).  Parity unpinned: the paper's own formula for anisotropic tensors (not printed), and the
+R1 weight s between its sphere (s = 1) and plane (s = 0) values.
 """
 
 import numpy as np
