@@ -195,8 +195,8 @@ __device__ __forceinline__ float acos3_cos(float opr) {
 }
 
 __device__ __forceinline__ float fast_cbrt(float v) {
-  // sign(v) |v|^(1/3) from the hardware log2/exp2 (a few ulp; the float64 Newton step on the
-  // collapse cubic that follows removes the error)
+  // sign(v) |v|^(1/3) from the hardware log2/exp2: a few float32 ulp, like the rest of the
+  // one-real-root branch's float32 arithmetic (no correction step follows)
   const float a = fabsf(v);
   const float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a) * (1.f / 3.f));
   return a == 0.f ? 0.f : copysignf(y, v);
