@@ -273,8 +273,8 @@ def oracle_phase(gpu_paths, out_json, md, threads, mem_bytes, cache=None):
     with open(out_json, "w") as fh:
         json.dump(rows, fh, indent=1)
         fh.write("\n")
-    keys = ["case", "radii", "F_rel_rms", "F_rel_max", "R_mismatch", "F_points", "psi1_rel_rms", "psi1_rel_max",
-            "psi2_rel_rms", "psi2_rel_max", "psi3_rel_rms", "psi3_rel_max", "psi_points"]
+    keys = ["case", "radii", "F_rel_rms", "F_rel_max", "R_mismatch", "R_mismatch_points", "F_points", "psi1_rel_rms",
+            "psi1_rel_max", "psi2_rel_rms", "psi2_rel_max", "psi3_rel_rms", "psi3_rel_max", "psi_points"]
     fmt = lambda v: f"{v:.2e}" if isinstance(v, float) else str(v)
     table = ["| " + " | ".join(keys) + " |", "|" + "---|" * len(keys)]
     table += ["| " + " | ".join(fmt(r.get(k, "")) for k in keys) + " |" for r in rows]
