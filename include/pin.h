@@ -255,7 +255,9 @@ pin_status pin_inverse_collapse_time(pin_plan plan, const void* T6, size_t count
  * no copy from host memory and no host wait -- only kernel launches on `stream`.  The workspace a
  * plan would allocate (11 half-spectrum slots, twiddle and window tables) is one static device
  * array of 96 MiB that the library holds on each device it runs on until the process ends; its
- * device address is looked up once per device on the first call there.  desc as for
+ * device address is looked up once per device on the first call there, so make that first call
+ * outside stream capture: later calls queue kernels only and can be captured into a HIP graph
+ * whose replays recompute the result.  desc as for
  * pin_plan_create (the spectrum fields are not used); dk, F and ridx as for pin_collapse_times
  * (device, caller-owned), with the same results.  Sizes: N <= 128 in PIN_FP32 and N <= 96 in
  * PIN_FP64 (any radius count); larger ones return PIN_ERR_UNSUPPORTED_SIZE before anything is

@@ -61,3 +61,44 @@ def test_noalloc_refuses_sizes_beyond_its_workspace(lib):
         assert e.value.status == lib.PIN_ERR_UNSUPPORTED_SIZE
         torch.cuda.synchronize()
         assert torch.all(F == 7.0).item() and torch.all(R == 3).item()
+
+
+def test_noalloc_replays_under_graph_capture(lib):
+    """The call captured into a HIP graph (after one eager call on the device, which looks up the
+    workspace's address) replays to the eager result bit for bit, three times, with an eager call
+    on another grid size rewriting the shared workspace before each replay."""
+    import torch
+
+    n, box, radii = 64, 100.0, W.radii_cells(16, 20.0, 0.75)
+    plan = lib.Plan(n, box, radii, prec=lib.PIN_FP32)
+    dk = plan.generate_field(101)
+    desc = lib.make_desc(n, box, radii, prec=lib.PIN_FP32)
+    F = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    R = torch.empty((n, n, n), dtype=torch.uint8, device="cuda")
+    lib.pin_collapse_times_noalloc(desc, dk.data_ptr(), F.data_ptr(), R.data_ptr(),
+                                   torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    F_eager, R_eager = F.clone(), R.clone()
+    other = lib.Plan(32, 50.0, W.radii_cells(6, 8.0, 0.75), prec=lib.PIN_FP32)
+    dk2 = other.generate_field(7)
+    desc2 = lib.make_desc(32, 50.0, W.radii_cells(6, 8.0, 0.75), prec=lib.PIN_FP32)
+    F2 = torch.empty((32, 32, 32), dtype=torch.float32, device="cuda")
+    R2 = torch.empty((32, 32, 32), dtype=torch.uint8, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        lib.pin_collapse_times_noalloc(desc, dk.data_ptr(), F.data_ptr(), R.data_ptr(),
+                                       torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        F.fill_(7.0)
+        R.fill_(3)
+        lib.pin_collapse_times_noalloc(desc2, dk2.data_ptr(), F2.data_ptr(), R2.data_ptr(),
+                                       torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(F, F_eager) and torch.equal(R, R_eager), f"replay {rep}"
+    del g
+    other.close()
+    plan.close()
