@@ -38,7 +38,9 @@ Pins (tests/test_oracle_collapse.py): delta_c and the sphere series against the 
 collapse, sphere and plane limits, homogeneity, the root finder against numpy.roots, and each
 coefficient of P against the Zel'dovich, 2LPT and 3LPT oracles (which the equations of motion
 pin).  Parity unpinned: the paper's own formula for anisotropic tensors (not printed), and the
-R1 weight s between its sphere (s = 1) and plane (s = 0) values.
+R1 weight s between its sphere (s = 1) and plane (s = 0) values; a numerically integrated
+homogeneous ellipsoid checks its size near the sphere (tests/test_oracle_ellipsoid.py: within
+4% for 3p/delta <= 0.07), not its exact form.
 """
 
 import numpy as np
