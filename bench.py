@@ -287,18 +287,23 @@ def kernel_times(B, plan, fn, repeats):
 
 
 def config_leg(B, W, name):
-    """Collapse times alone on another workload: median of 5 after 2 warm-ups (HIP events on the
-    plan's stream), then one call with per-launch events for the three passes' durations and
-    their algorithmic GB/s."""
+    """Collapse times alone on another workload (collapse_leg)."""
+    cfg = W.CONFIGS[name]
+    prec = B.PIN_FP64 if cfg["prec"] == "fp64" else B.PIN_FP32
+    radii = W.config_radii(cfg)
+    out = collapse_leg(B, W, cfg["n"], cfg["box"], radii, prec, cfg["seed"])
+    return {"workload": f"{cfg['n']}^3 grid, {cfg['box']:g} Mpc/h, {len(radii)} radii {cfg['r_max']:g}->{cfg['r_min']:g} "
+                        f"cells, collapse times only", "precision": cfg["prec"], **out}
+
+
+def collapse_leg(B, W, n, box, radii, prec, seed):
+    """Collapse times alone: median of 5 after 2 warm-ups (HIP events on the plan's stream), then
+    one call with per-launch events for the three passes' durations and their algorithmic GB/s."""
     import torch
 
-    cfg = W.CONFIGS[name]
-    n, box = cfg["n"], cfg["box"]
-    radii = W.config_radii(cfg)
-    prec = B.PIN_FP64 if cfg["prec"] == "fp64" else B.PIN_FP32
     plan = B.Plan(n, box, radii, W.SIGMA8, W.GAMMA, W.NS, prec)
     real_bytes = 8 if prec == B.PIN_FP64 else 4
-    dk = plan.generate_field(cfg["seed"])
+    dk = plan.generate_field(seed)
     F = torch.empty((n, n, n), dtype=plan.real, device="cuda")
     R = torch.empty((n, n, n), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
@@ -327,10 +332,27 @@ def config_leg(B, W, name):
     del dk, F, R
     plan.close()
     torch.cuda.empty_cache()
-    return {"workload": f"{n}^3 grid, {box:g} Mpc/h, {len(radii)} radii {cfg['r_max']:g}->{cfg['r_min']:g} cells, "
-                        f"collapse times only", "precision": cfg["prec"], "collapse_ms": round(ms, 2),
-            "updates_per_s": n ** 3 * len(radii) / (ms * 1e-3), "runs_ms": [round(x, 2) for x in runs],
-            "passes": passes}
+    return {"collapse_ms": round(ms, 2), "updates_per_s": n ** 3 * len(radii) / (ms * 1e-3),
+            "runs_ms": [round(x, 2) for x in runs], "passes": passes}
+
+
+def size_sweep(B, W):
+    """Collapse times alone at every supported grid size from 64^3, float32 and float64 plans:
+    16 radii from min(60, N/8) to 0.75 cells, 2 Mpc/h cells; one JSON line."""
+    import torch
+
+    torch.cuda.set_device(0)
+    rows = []
+    for prec, name in ((B.PIN_FP32, "fp32"), (B.PIN_FP64, "fp64")):
+        for n in [m for m in range(64, 1025) if B.pin_size_supported(m)]:
+            radii = W.radii_cells(16, min(60.0, n / 8.0), 0.75)
+            r = collapse_leg(B, W, n, 2.0 * n, radii, prec, 11)
+            rows.append({"n": n, "precision": name, "radii": len(radii), **r})
+            print(f"[bench] sweep {name} N={n}: {r['collapse_ms']} ms, {r['updates_per_s']:.3e} updates/s",
+                  file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "collapse-only grid-point x radius updates/s by grid size", "unit": "updates/s",
+                      "higher_is_better": True, "n_gpus": 1, "data": "synthetic (seeded BBKS Gaussian field)",
+                      "sweep": rows}))
 
 
 def main():
@@ -341,6 +363,8 @@ def main():
     ap.add_argument("--config", default="c512_fp32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="only the collapse-only sweep over grid sizes (its own JSON line)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-quick", action="store_true",
                     help="short serving trace (10 + 60 requests) instead of the full 20 + 300")
@@ -359,6 +383,9 @@ def main():
     from paper_1305_1505_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.size_sweep:
+        size_sweep(B, W)
+        return
     cfg = W.CONFIGS[args.config]
     n, box, seed = cfg["n"], cfg["box"], cfg["seed"]
     radii = W.config_radii(cfg)
