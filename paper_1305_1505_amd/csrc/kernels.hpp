@@ -79,8 +79,10 @@ struct Strided {
   // one transform's data live, within 64 VGPRs); otherwise 4 (float64 tiles are LDS-bound there)
   static constexpr int WPE = (sizeof(V) == 8 && E::K0 == 1 && E::SAME && E::max_held() <= E::R0) ? 8 : 4;
   // the float64 x pass keeps three outputs' multipliers and a transform live: at 4 waves per SIMD
-  // it spills; 2 waves (1.37 -> 1.21 ms at 512^3)
-  static constexpr int XWPE = sizeof(V) == 16 ? 2 : WPE;
+  // it spills; 2 waves (1.37 -> 1.21 ms at 512^3).  The float32 Hessian x pass of workgroups
+  // under 1024 threads (64^3, 256^3: 64 bytes a lane at 64 VGPRs, which made the 256^3 pass
+  // fetch 5.6x its input) gets 6 waves per SIMD (80 VGPRs; three 512-thread workgroups a CU).
+  static constexpr int XWPE = sizeof(V) == 16 ? 2 : (WPE == 8 && T < 1024 ? 6 : WPE);
   static constexpr int GRID = N * NZT;
   static constexpr size_t HSLOT = (size_t)N * N * HZ;
 };
