@@ -38,6 +38,31 @@ struct CollapseConst {
   double sphere_gain;
 };
 
+// Full-precision float64 reciprocal and reciprocal square root from the hardware estimates
+// (about 2^-23 relative) and two refinement steps, each of which squares the relative error: a
+// few ulp, against the library's correctly rounded division and square root sequences.
+__device__ __forceinline__ double rcp_full(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq_full(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+// sign(v) |v|^(1/3): the float32 hardware log2/exp2 estimate, then two Newton steps in float64
+// (the library cube root outside the range where the float32 estimate is a normal number)
+__device__ __forceinline__ double cbrt_full(double v) {
+  const double a = fabs(v);
+  if (a == 0.0) return 0.0;
+  if (!(a > 1e-30 && a < 1e30)) return cbrt(v);
+  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)a) * (1.f / 3.f));
+  y = y - (y * y * y - a) * (1.0 / 3.0) * rcp_full(y * y);
+  y = y - (y * y * y - a) * (1.0 / 3.0) * rcp_full(y * y);
+  return copysign(y, v);
+}
+
 __device__ __forceinline__ double cubic_largest_real_root(double a, double b, double c) {
   // depressed cubic t^3 + p t + q with F = t - a/3
   const double a3 = a * (1.0 / 3.0);
@@ -51,11 +76,12 @@ __device__ __forceinline__ double cubic_largest_real_root(double a, double b, do
     // three real roots (p < 0): t_k = 2 r cos(theta/3 - 2 pi k/3), cos(theta) = -hq / r^3; the
     // largest from the polynomial in sqrt(1 + cos theta) (within 1.1e-8 of it; the Newton steps
     // below polish it) unless the two largest roots nearly coincide
-    const double r = sqrt(-p3);
-    double cth = -hq / (r * r * r);
+    const double qr = rsq_full(-p3);
+    const double r = -p3 * qr;
+    double cth = -hq * (qr * qr * qr);
     cth = fmin(1.0, fmax(-1.0, cth));
     if (cth > -1.0 + 1e-8) {
-      const double u = sqrt(1.0 + cth);
+      const double u = (1.0 + cth) * rsq_full(1.0 + cth);
       double cu = (double)kAcos3U[8];
 #pragma unroll
       for (int k = 7; k >= 0; --k) cu = fma(cu, u, (double)kAcos3U[k]);
@@ -64,8 +90,9 @@ __device__ __forceinline__ double cubic_largest_real_root(double a, double b, do
       t = 2.0 * r * cos(acos(cth) * (1.0 / 3.0));
     }
   } else {
-    const double u = cbrt(-hq - copysign(sqrt(disc), hq));
-    t = (u != 0.0) ? (u - p3 / u) : 0.0;
+    const double sd = disc > 0.0 ? disc * rsq_full(disc) : 0.0;
+    const double u = cbrt_full(-hq - copysign(sd, hq));
+    t = (u != 0.0) ? (u - p3 * rcp_full(u)) : 0.0;
   }
   double x = t - a3;
 #pragma unroll
@@ -135,11 +162,12 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
   const double bxx = xx - m, byy = yy - m, bzz = zz - m;
   const double off = xy * xy + xz * xz + yz * yz;
   const double p2 = (bxx * bxx + byy * byy + bzz * bzz + 2.0 * off) * (1.0 / 6.0);
-  const double p = sqrt(p2);
+  const double qp = p2 > 0.0 ? rsq_full(p2) : 0.0;
+  const double p = p2 * qp;
   double l1 = m;
   if (p2 > 0.0) {
     const double detb = bxx * (byy * bzz - yz * yz) - xy * (xy * bzz - yz * xz) + xz * (xy * yz - byy * xz);
-    double r = detb / (2.0 * p2 * p);
+    double r = 0.5 * detb * (qp * qp * qp);
     r = fmin(1.0, fmax(-1.0, r));
     if (r > -1.0 + 1e-5) {
       // c(r) = cos(arccos(r)/3) from its polynomial in sqrt(1 + r) (within 1.1e-8), then Newton
@@ -147,7 +175,7 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
       // two largest roots are at least ~5e-3 p apart): from 2e-8 p two steps reach the root of
       // the computed polynomial, which the rounding of p^2 and det B moves by ~1e-16 p / sqrt(1 + r)
       // (3e-14 p at the switch; closer to r = -1 the rotations below are backward stable)
-      const double u = sqrt(1.0 + r);
+      const double u = (1.0 + r) * rsq_full(1.0 + r);
       double c = (double)kAcos3U[8];
 #pragma unroll
       for (int k = 7; k >= 0; --k) c = fma(c, u, (double)kAcos3U[k]);
@@ -169,7 +197,7 @@ __device__ __forceinline__ double collapse_point(double xx, double xy, double xz
   const double root = cubic_largest_real_root(ca, cb, cc0);
   const double fe3 = root > 0.0 ? root : 0.0;
   double s = 0.0;
-  if (delta > 0.0) s = fmin(1.0, fmax(0.0, 1.0 - 3.0 * p / delta));
+  if (delta > 0.0) s = fmin(1.0, fmax(0.0, 1.0 - 3.0 * p * rcp_full(delta)));
   return fe3 * (1.0 + cc.sphere_gain * s);
 }
 
