@@ -4,6 +4,7 @@
     python -m paper_1305_1505_amd.profile_summary traffic <fetch counter_collection.csv>
                                                          <write counter_collection.csv> <out.json> [out.md]
     python -m paper_1305_1505_amd.profile_summary issue <SQ counter_collection.csv> <out.json> [out.md]
+    python -m paper_1305_1505_amd.profile_summary overlap <kernel_trace.csv>   (serving concurrency)
     (--n=<N> anywhere: the passes of grid size N instead of 512)
 
 `trace` turns a `rocprofv3 --kernel-trace --stats --output-format csv` kernel-stats file into a
@@ -158,6 +159,63 @@ def trace_table(stats_csv):
     return "\n".join(lines)
 
 
+def overlap(trace_csv, window_s=0.5, dense=0.8):
+    """Concurrency of the served requests in a `rocprofv3 --kernel-trace` file: kernels on the
+    serving slots' streams (every stream but the default one), the time with kernels of k distinct
+    streams in flight, over the whole trace and from the first window of `window_s` seconds that
+    is busy more than `dense` of the time (the saturated replay, which submits every request at
+    once)."""
+    ev = []
+    for r in _rows(trace_csv):
+        if r["Stream_Id"] == "0":
+            continue
+        ev.append((int(r["Start_Timestamp"]), 1, r["Stream_Id"]))
+        ev.append((int(r["End_Timestamp"]), -1, r["Stream_Id"]))
+    ev.sort()
+    active, last, spans = {}, None, []
+    for t, d, st in ev:
+        if last is not None and t > last:
+            spans.append((last, t, sum(1 for v in active.values() if v > 0)))
+        active[st] = active.get(st, 0) + d
+        last = t
+
+    def dist(t_from):
+        out = {}
+        for a, b, k in spans:
+            if b > t_from:
+                out[k] = out.get(k, 0) + (b - max(a, t_from))
+        return out
+
+    w = int(window_s * 1e9)
+    busy_by_window = {}
+    for a, b, k in spans:
+        t = a
+        while t < b:
+            e = min(b, (t // w + 1) * w)
+            if k >= 1:
+                busy_by_window[t // w] = busy_by_window.get(t // w, 0) + (e - t)
+            t = e
+    dense_w = sorted(x for x, v in busy_by_window.items() if v > dense * w)
+    res = {"all": dist(spans[0][0]) if spans else {}}
+    if dense_w:
+        res["saturated"] = dist(dense_w[0] * w)
+        res["saturated_from_s"] = (dense_w[0] * w - spans[0][0]) / 1e9
+    return res
+
+
+def overlap_table(res):
+    lines = ["| part | busy s | idle s | 1 request | 2 | 3 | 4 or more |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for part in ("all", "saturated"):
+        d = res.get(part)
+        if not d:
+            continue
+        busy = sum(v for k, v in d.items() if k >= 1)
+        frac = lambda lo, hi=None: sum(v for k, v in d.items() if k >= lo and (hi is None or k <= hi)) / busy
+        lines.append(f"| {part} | {busy / 1e9:.3f} | {d.get(0, 0) / 1e9:.3f} | {frac(1, 1):.3f} | {frac(2, 2):.3f} | "
+                     f"{frac(3, 3):.3f} | {frac(4):.3f} |")
+    return "\n".join(lines)
+
+
 def main(argv):
     for a in [a for a in argv if a.startswith("--n=")]:
         set_grid_size(int(a[4:]))
@@ -178,6 +236,8 @@ def main(argv):
             with open(argv[3], "a") as fh:
                 fh.write(table + "\n")
         print(table)
+    elif len(argv) >= 2 and argv[0] == "overlap":
+        print(overlap_table(overlap(argv[1])))
     elif len(argv) >= 4 and argv[0] == "traffic":
         t = traffic(argv[1], argv[2])
         with open(argv[3], "w") as fh:
